@@ -1,0 +1,124 @@
+/*
+ * rsagpu.h - C ABI of the MI355X (gfx950) batched RSA modular-exponentiation
+ * library (librsagpu.so).
+ *
+ * The library computes, for many independent messages at once, the RSA
+ * transformations C = M^e mod n and M = C^d mod n (paper, Section 2 and
+ * Sections 3.2-3.3), one exponentiation per message, all messages in
+ * parallel (the data-parallel decomposition of the paper's Section 6).
+ *
+ * Conventions shared by every entry point:
+ *   - A big integer is an array of little-endian 32-bit limbs, limb 0 least
+ *     significant.  A batch of `count` integers of `limbs` limbs each is
+ *     message-major: element i occupies words [i*limbs, (i+1)*limbs).
+ *   - Every data pointer is a DEVICE pointer owned by the caller (for
+ *     instance the storage of a torch tensor).  The library never frees or
+ *     keeps it past the call's stream work.
+ *   - Work is enqueued on `stream` (NULL = the null stream) and is
+ *     asynchronous: the call returns before the results exist.  No entry
+ *     point synchronises the device except rsa_device_errors.
+ *   - No entry point allocates device memory per call: operands and the
+ *     window table of each exponentiation live in registers and LDS.
+ *   - Host-checkable errors are returned before any HIP call.  Per-element
+ *     data errors (an even or unit modulus, p <= q for CRT) write 0 to that
+ *     element's output and increment a per-device counter that
+ *     rsa_device_errors reads.
+ *   - The ABI is thread-safe for calls on distinct streams.  Results are
+ *     exact: every output is the unique residue in [0, modulus).
+ */
+#ifndef RSAGPU_H
+#define RSAGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSA_OK = 0,
+    RSA_EINVAL = -1,   /* null pointer, bad count or bad option            */
+    RSA_ELIMBS = -2,   /* limb width outside the supported range           */
+    RSA_ENOMEM = -3,   /* device memory exhausted                          */
+    RSA_EHIP = -4,     /* a HIP runtime call failed                        */
+    RSA_EKEY = -5      /* malformed key material                           */
+} rsa_status;
+
+/* Largest limb width accepted (4096-bit operands). */
+#define RSA_MAX_LIMBS 128
+
+/*
+ * Batched modular exponentiation (paper, Section 2: C = M^e mod n; the same
+ * operation with d decrypts, Section 11).
+ *
+ *   out[i] = base[i] ^ exp[i] mod mod[i],   0 <= i < count
+ *
+ * base, exp, mod, out: count * limbs words each (device, message-major).
+ * base may be >= mod (it is reduced); exp == 0 gives 1 mod n.  Every mod[i]
+ * must be odd and > 1 (Montgomery arithmetic); an even modulus, or a
+ * modulus equal to 1, is a data error (output 0, counter incremented;
+ * for mod == 1 the output 0 is also the correct value and is not counted).
+ * out may be the same buffer as base; other overlap is undefined.
+ * 1 <= limbs <= RSA_MAX_LIMBS; count == 0 is a no-op returning RSA_OK.
+ * Montgomery constants are derived per element on the device; for many
+ * messages under one key prefer the resident-key entry points below.
+ */
+int rsa_modexp_batch(const uint32_t *base, const uint32_t *exp, const uint32_t *mod,
+                     uint32_t *out, size_t count, int limbs, hipStream_t stream);
+
+/*
+ * Batched RSA decryption by the Chinese remainder theorem.
+ *
+ *   out[i] = c[i] ^ d mod (p[i] * q[i])
+ *
+ * computed as m_p = c^dp mod p and m_q = c^dq mod q followed by Garner's
+ * recombination m = m_q + q * (qinv * (m_p - m_q) mod p).  The result equals
+ * the paper's plain decryption M = C^d mod n (Section 2) for every
+ * c in [0, n) when d*e = 1 mod phi(n) and dp = d mod (p-1), dq = d mod (q-1).
+ *
+ * c, out: count * limbs words; p, q, dp, dq, qinv: count * (limbs/2) words
+ * (device, message-major).  limbs is the width of the modulus n = p*q and
+ * must be even, 2 <= limbs <= RSA_MAX_LIMBS.  Convention p > q and
+ * qinv = q^-1 mod p; p, q odd and > 1.  Violations are data errors.
+ * c must be < p*q (it is the caller's ciphertext).
+ */
+int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *q,
+                          const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,
+                          uint32_t *out, size_t count, int limbs, hipStream_t stream);
+
+/*
+ * Execution plan used for a limb width: lanes per exponentiation (G), limbs
+ * per lane (limbs_per_lane = padded_limbs / G), fixed-window width (bits of
+ * exponent per table lookup, paper Section 3.6.4), the padded limb width the
+ * kernel runs at, and the LDS bytes per 64-lane workgroup.  kind: 0 = plain
+ * exponentiation, 1 = CRT half (modulus of `limbs` limbs).  Pure host query.
+ */
+typedef struct {
+    int padded_limbs;
+    int lanes_per_op;
+    int limbs_per_lane;
+    int window_bits;
+    int lds_bytes;
+} rsa_plan;
+
+int rsa_get_plan(int limbs, int kind, rsa_plan *plan);
+
+/*
+ * Number of per-element data errors counted on the current device since the
+ * last call, then reset to zero.  Synchronises `stream` first.
+ */
+int rsa_device_errors(hipStream_t stream, uint64_t *n_bad);
+
+/* Static text for a status code. */
+const char *rsa_status_str(int status);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int rsa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSAGPU_H */

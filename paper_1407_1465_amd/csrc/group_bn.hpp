@@ -1,0 +1,495 @@
+// Lane-group multi-precision arithmetic for CDNA4 (gfx950, wave64).
+//
+// One big integer of S 32-bit limbs is spread over a group of G consecutive
+// lanes of a wavefront; lane r of the group holds limbs [r*L, r*L + L), with
+// L = S / G.  A wave therefore works on NG = 64 / G integers at once.  Every
+// function here is called by all 64 lanes of the wave in lockstep; lanes of
+// different groups work on different integers.
+//
+// Montgomery multiplication (Montgomery 1985) is organised as coarsely
+// integrated operand scanning (CIOS, Koc, Acar and Kaliski 1996): for each
+// limb b_i of the multiplier, add a*b_i, derive m = t_0 * (-n^-1) mod 2^32,
+// add m*n and drop the (now zero) bottom limb.  The distribution over lanes
+// and the carry handling are this library's own:
+//
+//   * each limb position of the running sum t is a 96-bit accumulator
+//     (a 64-bit register pair plus a carry-count word), so every 32x32-bit
+//     product costs one v_mad_u64_u32 (carry-out to VCC) and one
+//     v_addc_co_u32 - no carry chain runs along the limbs inside the loop;
+//   * after each step every lane folds the high 64 bits of its bottom
+//     position into the next position, so the word that moves to the lane
+//     below is a plain 32-bit value; lane 0 of the group drops it (it is the
+//     zero word of the Montgomery shift);
+//   * limb positions rotate through the registers (position j of step k is
+//     register (j + k) mod L), so the shift by one limb costs no moves;
+//   * carries are resolved once per product, across lanes, with one wave
+//     ballot for "generate" and one for "propagate" and a 64-bit scalar add
+//     (the carry-lookahead identity carries = (A + B) ^ A ^ B).
+//
+// The multiplier b is read from LDS (group-uniform addresses, so a broadcast
+// within the group); the multiplicand a and the modulus n sit in VGPRs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsagpu {
+
+__device__ __forceinline__ unsigned lane_id() { return __lane_id(); }
+
+template <int G>
+__device__ __forceinline__ unsigned grp_lane() { return lane_id() & (G - 1); }
+
+template <int G>
+__device__ __forceinline__ unsigned grp_index() { return lane_id() / G; }
+
+// Bit mask of the lanes that are the top lane of their group.
+template <int G>
+__device__ __forceinline__ constexpr uint64_t top_lanes_mask()
+{
+    uint64_t m = 0;
+    for (int l = G - 1; l < 64; l += G) m |= 1ull << l;
+    return m;
+}
+
+// ---- cross-lane moves inside a group -----------------------------------
+
+// Value of lane `src` of this lane's group.
+template <int G>
+__device__ __forceinline__ uint32_t grp_bcast(uint32_t v, int src)
+{
+    if constexpr (G == 1) return v;
+    else return (uint32_t)__shfl((int)v, src, G);
+}
+
+// Lane r receives lane r+1's value; the group's top lane receives 0.
+template <int G>
+__device__ __forceinline__ uint32_t grp_from_above(uint32_t v)
+{
+    if constexpr (G == 1) return 0;
+    else {
+        uint32_t u = (uint32_t)__shfl_down((int)v, 1, G);
+        return grp_lane<G>() == G - 1 ? 0u : u;
+    }
+}
+
+// Lane r receives lane r-1's value; the group's lane 0 receives 0.
+template <int G>
+__device__ __forceinline__ uint32_t grp_from_below(uint32_t v)
+{
+    if constexpr (G == 1) return 0;
+    else {
+        uint32_t u = (uint32_t)__shfl_up((int)v, 1, G);
+        return grp_lane<G>() == 0 ? 0u : u;
+    }
+}
+
+// Carry (or borrow) into each lane of a multi-lane addition.  `gen`: this
+// lane's own limbs produced a carry out; `prop`: an incoming carry would run
+// through all of this lane's limbs.  Carries never cross a group boundary:
+// what leaves a group's top lane is that group's overflow, handled by the
+// caller.
+template <int G>
+__device__ __forceinline__ uint32_t grp_carry_in(bool gen, bool prop)
+{
+    if constexpr (G == 1) return 0;
+    else {
+        const uint64_t keep = ~top_lanes_mask<G>();
+        const uint64_t gm = __ballot(gen) & keep;
+        const uint64_t pm = __ballot(prop) & keep;
+        const uint64_t a = gm | pm;
+        const uint64_t c = (a + gm) ^ a ^ gm;
+        return (uint32_t)(c >> lane_id()) & 1u;
+    }
+}
+
+// Every lane of a group gets the flag of its group's top lane.
+template <int G>
+__device__ __forceinline__ bool grp_top_flag(bool f)
+{
+    if constexpr (G == 1) return f;
+    else {
+        const uint64_t m = __ballot(f && grp_lane<G>() == G - 1);
+        const unsigned top = (lane_id() & ~(unsigned)(G - 1)) + (G - 1);
+        return (m >> top) & 1ull;
+    }
+}
+
+// True in every lane of a group when the predicate holds in any lane of it.
+template <int G>
+__device__ __forceinline__ bool grp_any(bool f)
+{
+    if constexpr (G == 1) return f;
+    else {
+        const uint64_t m = __ballot(f);
+        const unsigned base = lane_id() & ~(unsigned)(G - 1);
+        const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1) << base);
+        return (m & gmask) != 0;
+    }
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t grp_max(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        uint32_t u = (uint32_t)__shfl_xor((int)v, o, G);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = (uint32_t)__shfl_xor((int)v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+// ---- single-lane limb helpers --------------------------------------------
+
+// {acc} += x*y as a 64-bit sum; the carry out of bit 63 is added to hi.
+__device__ __forceinline__ void mac(uint64_t &acc, uint32_t &hi, uint32_t x, uint32_t y)
+{
+    asm("v_mad_u64_u32 %0, vcc, %2, %3, %0\n\t"
+        "v_addc_co_u32 %1, vcc, 0, %1, vcc"
+        : "+v"(acc), "+v"(hi)
+        : "v"(x), "v"(y)
+        : "vcc");
+}
+
+// (acc, hi) += x  where x is a 64-bit value at the same weight as acc.
+__device__ __forceinline__ void add96(uint64_t &acc, uint32_t &hi, uint32_t xlo, uint32_t xhi)
+{
+    uint32_t a0 = (uint32_t)acc, a1 = (uint32_t)(acc >> 32);
+    uint64_t t = (uint64_t)a0 + xlo;
+    a0 = (uint32_t)t;
+    t = (uint64_t)a1 + xhi + (uint32_t)(t >> 32);
+    a1 = (uint32_t)t;
+    hi += (uint32_t)(t >> 32);
+    acc = ((uint64_t)a1 << 32) | a0;
+}
+
+// -n0^-1 mod 2^32 for odd n0 (Newton-Hensel lifting: x <- x(2 - n0 x)
+// doubles the number of correct low bits; n0 itself is correct to 3 bits).
+__device__ __forceinline__ uint32_t neg_inv32(uint32_t n0)
+{
+    uint32_t x = n0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x *= 2u - n0 * x;
+    return 0u - x;
+}
+
+// ---- LDS operand layout ---------------------------------------------------
+//
+// An operand buffer holds one S-limb integer for each of the NG groups of a
+// wave.  Limb i of group g is at word ((i / V) * NG + g) * V + i % V, so a
+// group reads V consecutive limbs with one vector load and, in every step,
+// the NG groups of a wave read NG different banks.
+template <int S, int G>
+struct Layout {
+    static constexpr int L = S / G;
+    static constexpr int NG = 64 / G;
+    static constexpr int V = (L % 4 == 0) ? 4 : ((L % 2 == 0) ? 2 : 1);
+    static constexpr int WORDS = S * NG;   // words of one operand buffer
+    __device__ static constexpr int at(int limb, int g) { return ((limb / V) * NG + g) * V + (limb % V); }
+};
+
+template <int V>
+struct VecT;
+template <> struct VecT<1> { typedef uint32_t T; };
+template <> struct VecT<2> { typedef uint2 T; };
+template <> struct VecT<4> { typedef uint4 T; };
+
+// Each lane stores its L limbs of x into the group's slot of buffer buf.
+template <int S, int G>
+__device__ __forceinline__ void lds_put(uint32_t *buf, const uint32_t (&x)[S / G])
+{
+    using Ly = Layout<S, G>;
+    const int g = grp_index<G>(), r = grp_lane<G>();
+#pragma unroll
+    for (int k = 0; k < Ly::L; k += Ly::V) {
+        typename VecT<Ly::V>::T v;
+        uint32_t *pv = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+        for (int u = 0; u < Ly::V; ++u) pv[u] = x[k + u];
+        *reinterpret_cast<typename VecT<Ly::V>::T *>(buf + Ly::at(r * Ly::L + k, g)) = v;
+    }
+}
+
+// Each lane loads its L limbs of group slot gs of buffer buf.
+template <int S, int G>
+__device__ __forceinline__ void lds_get(uint32_t (&x)[S / G], const uint32_t *buf, int gs)
+{
+    using Ly = Layout<S, G>;
+    const int r = grp_lane<G>();
+#pragma unroll
+    for (int k = 0; k < Ly::L; k += Ly::V) {
+        typename VecT<Ly::V>::T v =
+            *reinterpret_cast<const typename VecT<Ly::V>::T *>(buf + Ly::at(r * Ly::L + k, gs));
+        const uint32_t *pv = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+        for (int u = 0; u < Ly::V; ++u) x[k + u] = pv[u];
+    }
+}
+
+// Orders the LDS traffic of the whole workgroup (one wave per workgroup).
+__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+
+// ---- group-wide add / subtract / compare -------------------------------
+
+// x += y over the group; returns the overflow bit in every lane of the group.
+template <int S, int G>
+__device__ __forceinline__ uint32_t grp_add(uint32_t (&x)[S / G], const uint32_t (&y)[S / G])
+{
+    constexpr int L = S / G;
+    uint32_t c = 0;
+    bool allones = true;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        uint64_t t = (uint64_t)x[j] + y[j] + c;
+        x[j] = (uint32_t)t;
+        c = (uint32_t)(t >> 32);
+        allones = allones && (x[j] == 0xFFFFFFFFu);
+    }
+    const uint32_t cin = grp_carry_in<G>(c != 0, allones);
+    uint32_t k = cin;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        uint64_t t = (uint64_t)x[j] + k;
+        x[j] = (uint32_t)t;
+        k = (uint32_t)(t >> 32);
+    }
+    return grp_top_flag<G>((c | k) != 0) ? 1u : 0u;
+}
+
+// d = x - y over the group; returns 1 in every lane of the group when x < y.
+template <int S, int G>
+__device__ __forceinline__ uint32_t grp_sub(uint32_t (&d)[S / G], const uint32_t (&x)[S / G],
+                                            const uint32_t (&y)[S / G])
+{
+    constexpr int L = S / G;
+    uint32_t b = 0;
+    bool allzero = true;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        uint64_t t = (uint64_t)x[j] - y[j] - b;
+        d[j] = (uint32_t)t;
+        b = (uint32_t)(t >> 32) & 1u;
+        allzero = allzero && (d[j] == 0u);
+    }
+    const uint32_t bin = grp_carry_in<G>(b != 0, allzero);
+    uint32_t k = bin;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        uint64_t t = (uint64_t)d[j] - k;
+        d[j] = (uint32_t)t;
+        k = (uint32_t)(t >> 32) & 1u;
+    }
+    return grp_top_flag<G>((b | k) != 0) ? 1u : 0u;
+}
+
+// x = (x + top * 2^(32S)) mod n for x + top*2^(32S) < 2n; `top` is read from
+// the group's top lane only (other lanes pass anything).
+template <int S, int G>
+__device__ __forceinline__ void grp_cond_sub(uint32_t (&x)[S / G], uint32_t top,
+                                             const uint32_t (&n)[S / G])
+{
+    constexpr int L = S / G;
+    uint32_t d[L];
+    const uint32_t borrow = grp_sub<S, G>(d, x, n);
+    const bool over = grp_top_flag<G>(top != 0);
+    const bool take = over || !borrow;
+#pragma unroll
+    for (int j = 0; j < L; ++j) x[j] = take ? d[j] : x[j];
+}
+
+// x = (x + y) mod n for x, y < n.
+template <int S, int G>
+__device__ __forceinline__ void grp_add_mod(uint32_t (&x)[S / G], const uint32_t (&y)[S / G],
+                                            const uint32_t (&n)[S / G])
+{
+    const uint32_t ovf = grp_add<S, G>(x, y);
+    grp_cond_sub<S, G>(x, ovf, n);
+}
+
+// x = (x - y) mod n for x, y < n.
+template <int S, int G>
+__device__ __forceinline__ void grp_sub_mod(uint32_t (&x)[S / G], const uint32_t (&y)[S / G],
+                                            const uint32_t (&n)[S / G])
+{
+    constexpr int L = S / G;
+    uint32_t d[L];
+    const uint32_t neg = grp_sub<S, G>(d, x, y);
+    uint32_t e[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) e[j] = d[j];
+    grp_add<S, G>(e, n);
+#pragma unroll
+    for (int j = 0; j < L; ++j) x[j] = neg ? e[j] : d[j];
+}
+
+// x = 2x mod n for x < n.
+template <int S, int G>
+__device__ __forceinline__ void grp_dbl_mod(uint32_t (&x)[S / G], const uint32_t (&n)[S / G])
+{
+    constexpr int L = S / G;
+    const uint32_t out = x[L - 1] >> 31;
+    const uint32_t in = grp_from_below<G>(out);
+#pragma unroll
+    for (int j = L - 1; j > 0; --j) x[j] = (x[j] << 1) | (x[j - 1] >> 31);
+    x[0] = (x[0] << 1) | in;
+    grp_cond_sub<S, G>(x, out, n);
+}
+
+// Highest set bit + 1 of the group's integer (0 for zero), in every lane.
+template <int S, int G>
+__device__ __forceinline__ uint32_t grp_bitlen(const uint32_t (&x)[S / G])
+{
+    constexpr int L = S / G;
+    uint32_t bl = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        if (x[j]) bl = (uint32_t)(32 * (grp_lane<G>() * L + j) + 32 - __clz(x[j]));
+    return grp_max<G>(bl);
+}
+
+// ---- normalisation of the redundant accumulator ------------------------
+
+// Turns the L 96-bit positions of each lane into S normalised limbs plus the
+// group's overflow (returned, meaningful in the top lane).  w receives the
+// limbs.
+template <int S, int G>
+__device__ __forceinline__ uint32_t grp_normalise(uint32_t (&w)[S / G], const uint64_t (&acc)[S / G],
+                                                  const uint32_t (&hi)[S / G])
+{
+    constexpr int L = S / G;
+    static_assert(L >= 2, "at least two limbs per lane");
+    uint32_t clo = 0, chi = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        uint64_t t = (uint64_t)(uint32_t)acc[j] + clo;
+        w[j] = (uint32_t)t;
+        t = (acc[j] >> 32) + (uint64_t)chi + (uint32_t)(t >> 32);
+        clo = (uint32_t)t;
+        chi = hi[j] + (uint32_t)(t >> 32);
+    }
+    // the 64-bit carry of each lane enters the lane above
+    const uint32_t rlo = grp_from_below<G>(clo), rhi = grp_from_below<G>(chi);
+    uint32_t own = (grp_lane<G>() == G - 1) ? clo : 0u;   // what leaves the group
+    uint64_t t = (uint64_t)w[0] + rlo;
+    w[0] = (uint32_t)t;
+    t = (uint64_t)w[1] + rhi + (uint32_t)(t >> 32);
+    w[1] = (uint32_t)t;
+    uint32_t k = (uint32_t)(t >> 32);
+#pragma unroll
+    for (int j = 2; j < L; ++j) {
+        t = (uint64_t)w[j] + k;
+        w[j] = (uint32_t)t;
+        k = (uint32_t)(t >> 32);
+    }
+    bool allones = true;
+#pragma unroll
+    for (int j = 0; j < L; ++j) allones = allones && (w[j] == 0xFFFFFFFFu);
+    const uint32_t cin = grp_carry_in<G>(k != 0, allones);
+    uint32_t k2 = cin;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        t = (uint64_t)w[j] + k2;
+        w[j] = (uint32_t)t;
+        k2 = (uint32_t)(t >> 32);
+    }
+    return own + k + k2 + (grp_lane<G>() == G - 1 ? chi : 0u);
+}
+
+// ---- Montgomery product -------------------------------------------------
+//
+// r = a * b * 2^(-32S) mod n, with a < 2^(32S) in registers, b < n in the
+// group's slot of LDS buffer bbuf (or a < n and b < 2^(32S)), n odd.
+// Mode Wide (used for the plain product of the CRT recombination): no
+// reduction; the bottom limb of each step is handed to `sink` instead.
+template <int S, int G>
+__device__ __forceinline__ void mont_mul(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
+                                         const uint32_t *bbuf, const uint32_t (&n)[S / G],
+                                         uint32_t n0inv)
+{
+    using Ly = Layout<S, G>;
+    constexpr int L = Ly::L, V = Ly::V;
+    const int g = grp_index<G>();
+    uint64_t acc[L];
+    uint32_t hi[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) { acc[j] = 0; hi[j] = 0; }
+
+    for (int i0 = 0; i0 < S; i0 += L) {
+        uint32_t bv[L];
+#pragma unroll
+        for (int k = 0; k < L; k += V) {
+            typename VecT<V>::T v = *reinterpret_cast<const typename VecT<V>::T *>(bbuf + Ly::at(i0 + k, g));
+            const uint32_t *pv = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+            for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
+        }
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            // position j of this step lives in register (j + k) % L
+#pragma unroll
+            for (int j = 0; j < L; ++j) mac(acc[(j + k) % L], hi[(j + k) % L], a[j], bv[k]);
+            const int p0 = k % L, p1 = (k + 1) % L;
+            const uint32_t m = grp_bcast<G>((uint32_t)acc[p0] * n0inv, 0);
+#pragma unroll
+            for (int j = 0; j < L; ++j) mac(acc[(j + k) % L], hi[(j + k) % L], m, n[j]);
+            add96(acc[p1], hi[p1], (uint32_t)(acc[p0] >> 32), hi[p0]);
+            const uint32_t in = grp_from_above<G>((uint32_t)acc[p0]);
+            acc[p0] = in;
+            hi[p0] = 0;
+        }
+    }
+    const uint32_t top = grp_normalise<S, G>(r, acc, hi);
+    grp_cond_sub<S, G>(r, top, n);
+}
+
+// Plain product used by the CRT recombination:
+//   (low, high) = init + a * b,   init < 2^(32S), a, b < 2^(32S)
+// b in LDS.  The S low limbs are produced one per step; lane 0 of the group
+// passes low limb i to sink(i, limb).  high receives the upper S limbs.
+template <int S, int G, typename Sink>
+__device__ __forceinline__ void mul_wide(uint32_t (&high)[S / G], const uint32_t (&init)[S / G],
+                                         const uint32_t (&a)[S / G], const uint32_t *bbuf, Sink sink)
+{
+    using Ly = Layout<S, G>;
+    constexpr int L = Ly::L, V = Ly::V;
+    const int g = grp_index<G>();
+    uint64_t acc[L];
+    uint32_t hi[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) { acc[j] = init[j]; hi[j] = 0; }
+
+    for (int i0 = 0; i0 < S; i0 += L) {
+        uint32_t bv[L];
+#pragma unroll
+        for (int k = 0; k < L; k += V) {
+            typename VecT<V>::T v = *reinterpret_cast<const typename VecT<V>::T *>(bbuf + Ly::at(i0 + k, g));
+            const uint32_t *pv = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+            for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
+        }
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+#pragma unroll
+            for (int j = 0; j < L; ++j) mac(acc[(j + k) % L], hi[(j + k) % L], a[j], bv[k]);
+            const int p0 = k % L, p1 = (k + 1) % L;
+            sink(i0 + k, (uint32_t)acc[p0]);
+            add96(acc[p1], hi[p1], (uint32_t)(acc[p0] >> 32), hi[p0]);
+            const uint32_t in = grp_from_above<G>((uint32_t)acc[p0]);
+            acc[p0] = in;
+            hi[p0] = 0;
+        }
+    }
+    grp_normalise<S, G>(high, acc, hi);
+}
+
+}  // namespace rsagpu

@@ -22,6 +22,7 @@ from __future__ import annotations
 import json
 import math
 import os
+import sys
 from dataclasses import dataclass, asdict
 from typing import Dict, List, Optional, Sequence
 
@@ -240,6 +241,10 @@ def make_keys(bits: int, seed: int, count: int, e: int = 65537,
     args = [(bits, derive_seed(seed, bits, j), e) for j in range(count)]
     if processes is None:
         processes = min(count, 16, os.cpu_count() or 1)
+    # no worker processes once this process has initialised a GPU
+    tmod = sys.modules.get("torch")
+    if tmod is not None and getattr(tmod, "cuda", None) is not None and tmod.cuda.is_initialized():
+        processes = 1
     if processes > 1 and count > 1 and bits >= 512:
         import multiprocessing as mp
         with mp.get_context("fork").Pool(processes) as pool:
@@ -328,7 +333,7 @@ class Workload:
     limbs: int
 
 
-def _messages_for_keys(keys: List[RSAKey], count: int, seed: int, tag: int):
+def messages_for_keys(keys: List[RSAKey], count: int, seed: int, tag: int):
     """Element i belongs to key i mod len(keys); per-key uniform draws."""
     K = len(keys)
     L = keys[0].limbs
@@ -343,8 +348,8 @@ def _messages_for_keys(keys: List[RSAKey], count: int, seed: int, tag: int):
 
 def single_size_workload(name: str, bits: int, nkeys: int, count: int, seed: int) -> Workload:
     keys = make_keys(bits, seed, nkeys)
-    key_of, msgs = _messages_for_keys(keys, count, seed, 1)
-    _, ctxt = _messages_for_keys(keys, count, seed, 2)
+    key_of, msgs = messages_for_keys(keys, count, seed, 1)
+    _, ctxt = messages_for_keys(keys, count, seed, 2)
     return Workload(name, seed, keys, key_of, msgs, ctxt, keys[0].limbs)
 
 

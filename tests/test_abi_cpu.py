@@ -1,0 +1,70 @@
+"""The C ABI on a host without a GPU: the library loads, exports every symbol
+include/rsagpu.h declares, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "rsagpu.h")
+LIB = os.path.join(ROOT, "paper_1407_1465_amd", "librsagpu.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsa_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("librsagpu.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert "rsa_modexp_batch" in names and "rsa_decrypt_crt_batch" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_header():
+    from paper_1407_1465_amd import rsagpu
+    assert sorted(rsagpu.EXPORTS) == declared_functions()
+
+
+def test_host_side_validation(lib):
+    P = ctypes.c_void_p
+    f = lib.rsa_modexp_batch
+    f.argtypes = [P, P, P, P, ctypes.c_size_t, ctypes.c_int, P]
+    dummy = P(16)
+    assert f(dummy, dummy, dummy, dummy, 4, 0, None) == -2          # limbs too small
+    assert f(dummy, dummy, dummy, dummy, 4, 129, None) == -2        # limbs too large
+    assert f(None, dummy, dummy, dummy, 4, 8, None) == -1           # null pointer
+    assert f(None, None, None, None, 0, 8, None) == 0               # empty batch
+    g = lib.rsa_decrypt_crt_batch
+    g.argtypes = [P] * 7 + [ctypes.c_size_t, ctypes.c_int, P]
+    assert g(*([dummy] * 7), 4, 63, None) == -2                     # odd width
+    assert g(*([dummy] * 6), None, 4, 64, None) == -1
+    assert g(*([None] * 7), 0, 64, None) == 0
+    s = lib.rsa_status_str
+    s.restype = ctypes.c_char_p
+    assert s(0) == b"ok" and s(-2) == b"limb width out of range"
+    assert lib.rsa_version() >= 100
+
+
+def test_plans_are_consistent():
+    from paper_1407_1465_amd import rsagpu
+    for limbs in range(1, 129):
+        for kind in (0, 1):
+            p = rsagpu.get_plan(limbs, kind)
+            assert p.padded_limbs >= limbs
+            assert p.lanes_per_op * p.limbs_per_lane == p.padded_limbs
+            assert p.limbs_per_lane >= 2 and 64 % p.lanes_per_op == 0
+            assert p.lds_bytes <= 64 * 1024
+    with pytest.raises(Exception):
+        rsagpu.get_plan(0, 0)

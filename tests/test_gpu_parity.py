@@ -1,0 +1,197 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Every result is compared element by element with the oracle on the same
+seeded inputs, at sizes that span several waves and a ragged tail; at the
+full workload sizes a seeded sample of outputs is checked against the oracle
+and the whole batch against the round-trip property (M^e)^d mod n = M.
+"""
+import random
+
+import numpy as np
+import pytest
+
+from paper_1407_1465_amd import workloads as W
+from gpu_util import dev, host, oracle_modexp, crt_operands, full_operands
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1407_1465_amd import rsagpu  # noqa: E402  (fails loudly if the library is missing)
+
+WIDTHS = [1, 2, 3, 4, 5, 8, 12, 16, 24, 31, 32, 48, 64, 96, 128]
+
+
+def _random_case(rng, limbs, count):
+    bits = 32 * limbs
+    mods, bases, exps = [], [], []
+    for i in range(count):
+        nb = bits if i % 3 else rng.randint(2, bits)
+        n = (rng.getrandbits(nb) | (1 << (nb - 1)) | 1)
+        if i % 7 == 3:
+            n = (1 << bits) - 1                     # top limb all ones
+        mods.append(n)
+        bases.append(rng.getrandbits(bits))         # may exceed n
+        kind = i % 5
+        if kind == 0:
+            e = rng.getrandbits(bits)
+        elif kind == 1:
+            e = rng.getrandbits(rng.randint(1, 24))
+        elif kind == 2:
+            e = 65537
+        elif kind == 3:
+            e = rng.getrandbits(max(1, bits // 2))
+        else:
+            e = rng.getrandbits(bits) | (1 << (bits - 1))
+        exps.append(e)
+    return [W.ints_to_limbs(v, limbs) for v in (bases, exps, mods)]
+
+
+@pytest.mark.parametrize("limbs", WIDTHS)
+def test_modexp_random_vs_oracle(limbs):
+    plan = rsagpu.get_plan(limbs, 0)
+    ng = 64 // plan.lanes_per_op
+    count = 2 * ng + 5 if limbs >= 64 else 3 * ng + 5        # several waves + a ragged tail
+    rng = random.Random(1000 + limbs)
+    B, E, M = _random_case(rng, limbs, count)
+    out = host(rsagpu.modexp(dev(B), dev(E), dev(M)))
+    want = oracle_modexp(B, E, M)
+    bad = np.nonzero((out != want).any(axis=1))[0]
+    assert bad.size == 0, "limbs=%d: %d mismatches, first at %d" % (limbs, bad.size, bad[0])
+    assert rsagpu.device_errors() == 0
+
+
+@pytest.mark.parametrize("limbs", [2, 32, 64])
+def test_modexp_special_cases(limbs):
+    rng = random.Random(7 + limbs)
+    bits = 32 * limbs
+    n = rng.getrandbits(bits) | (1 << (bits - 1)) | 1
+    e = rng.getrandbits(bits) | 1
+    cases = [
+        (5, 0, n), (0, 0, n), (12345, 1, n), (n + 5, 1, n), (0, e, n), (1, e, n),
+        (n - 1, e, n), (n - 1, e - 1, n), (n - 1, 2, n), (2, e, 3), (5, 3, 3),
+        ((1 << bits) - 1, e, n), ((1 << bits) - 1, (1 << bits) - 1, (1 << bits) - 1),
+        (7, 5, 1),                                      # n = 1: result 0, not an error
+    ]
+    B, E, M = (W.ints_to_limbs([c[i] for c in cases], limbs) for i in range(3))
+    out = host(rsagpu.modexp(dev(B), dev(E), dev(M)))
+    got = W.limbs_to_ints(out)
+    assert got == [pow(b, x, m) for b, x, m in cases]
+    assert got == W.limbs_to_ints(oracle_modexp(B, E, M))
+    assert rsagpu.device_errors() == 0
+
+
+def test_modexp_data_errors():
+    limbs = 4
+    cases = [(3, 5, 10), (3, 5, 0), (3, 5, 97), (2, 2, 1 << 64)]
+    B, E, M = (W.ints_to_limbs([c[i] for c in cases], limbs) for i in range(3))
+    out = W.limbs_to_ints(host(rsagpu.modexp(dev(B), dev(E), dev(M))))
+    assert out == [0, 0, pow(3, 5, 97), 0]
+    assert rsagpu.device_errors() == 3
+    assert rsagpu.device_errors() == 0
+
+
+def test_modexp_in_place_and_empty():
+    limbs = 8
+    rng = random.Random(3)
+    B, E, M = _random_case(rng, limbs, 70)
+    want = oracle_modexp(B, E, M)
+    b = dev(B)
+    rsagpu.modexp(b, dev(E), dev(M), out=b)
+    assert np.array_equal(host(b), want)
+    empty = dev(np.zeros((0, limbs), dtype=np.uint32))
+    rsagpu.modexp(empty, empty, empty)
+
+
+def test_workload_rsa64_full_size():
+    """64-bit key, 4096 messages: encrypt and full-d decrypt, all checked."""
+    w = W.workload_c1()
+    k = w.keys[0]
+    L = w.limbs
+    n = full_operands(w.keys, w.key_of, L, "n")
+    e = full_operands(w.keys, w.key_of, L, "e")
+    d = full_operands(w.keys, w.key_of, L, "d")
+    c = host(rsagpu.modexp(dev(w.msgs), dev(e), dev(n)))
+    assert np.array_equal(c, oracle_modexp(w.msgs, e, n))
+    m = host(rsagpu.modexp(dev(c), dev(d), dev(n)))
+    assert np.array_equal(m, w.msgs)                       # round trip
+    dec = host(rsagpu.modexp(dev(w.ctxt), dev(d), dev(n)))
+    assert np.array_equal(dec, oracle_modexp(w.ctxt, d, n))
+    assert W.limbs_to_ints(c[:4]) == [pow(x, k.e, k.n) for x in W.limbs_to_ints(w.msgs[:4])]
+
+
+def test_workload_rsa1024_sampled_and_roundtrip():
+    """1024-bit key, 65536 messages: full-d decryption sampled against the
+    oracle; the whole batch round-trips."""
+    w = W.workload_c2()
+    L = w.limbs
+    n = full_operands(w.keys, w.key_of, L, "n")
+    e = full_operands(w.keys, w.key_of, L, "e")
+    d = full_operands(w.keys, w.key_of, L, "d")
+    dec = host(rsagpu.modexp(dev(w.ctxt), dev(d), dev(n)))
+    idx = np.random.default_rng(5).choice(len(w.ctxt), 192, replace=False)
+    assert np.array_equal(dec[idx], oracle_modexp(w.ctxt[idx], d[idx], n[idx]))
+    c = rsagpu.modexp(dev(w.msgs), dev(e), dev(n))
+    assert np.array_equal(host(c)[idx], oracle_modexp(w.msgs[idx], e[idx], n[idx]))
+    m = host(rsagpu.modexp(c, dev(d), dev(n)))
+    assert np.array_equal(m, w.msgs)
+
+
+@pytest.mark.parametrize("bits,count", [(64, 300), (256, 130), (1024, 90), (2048, 70)])
+def test_crt_vs_oracle_plain_decrypt(bits, count):
+    """CRT decryption equals the oracle's plain C^d mod n on every element."""
+    keys = W.make_keys(bits, 77 + bits, 4)
+    L = keys[0].limbs
+    key_of = np.arange(count) % 4
+    rng = random.Random(bits)
+    cs = [rng.randrange(keys[i % 4].n) for i in range(count)]
+    cs[0], cs[1], cs[2] = 0, 1, keys[2].n - 1
+    cs[3] = keys[3].p                                       # gcd(c, n) > 1
+    cs[4] = keys[0].q * 5 % keys[0].n
+    C = W.ints_to_limbs(cs, L)
+    p, q, dp, dq, qi = crt_operands(keys, key_of, L)
+    out = host(rsagpu.decrypt_crt(dev(C), dev(p), dev(q), dev(dp), dev(dq), dev(qi)))
+    n = full_operands(keys, key_of, L, "n")
+    d = full_operands(keys, key_of, L, "d")
+    want = oracle_modexp(C, d, n)
+    bad = np.nonzero((out != want).any(axis=1))[0]
+    assert bad.size == 0, "%d mismatches, first at %d" % (bad.size, bad[0] if bad.size else -1)
+    assert rsagpu.device_errors() == 0
+
+
+def test_crt_rejects_p_not_greater_than_q():
+    keys = W.make_keys(128, 5, 1)
+    k = keys[0]
+    L = k.limbs
+    h = L // 2
+    C = W.ints_to_limbs([5, 7], L)
+    # element 0 swapped (p < q), element 1 correct
+    p = W.ints_to_limbs([k.q, k.p], h)
+    q = W.ints_to_limbs([k.p, k.q], h)
+    dp = W.ints_to_limbs([k.dq, k.dp], h)
+    dq = W.ints_to_limbs([k.dp, k.dq], h)
+    qi = W.ints_to_limbs([pow(k.p, -1, k.q), k.qinv], h)
+    out = W.limbs_to_ints(host(rsagpu.decrypt_crt(dev(C), dev(p), dev(q), dev(dp), dev(dq), dev(qi))))
+    assert out == [0, pow(7, k.d, k.n)]
+    assert rsagpu.device_errors() == 1
+
+
+def test_workload_rsa2048_crt_sampled_and_roundtrip():
+    """64 keys of 2048 bits, 16384 messages round-robin: CRT decryption of the
+    whole batch sampled against the oracle, plus the encrypt/decrypt round trip."""
+    w = W.workload_c3()
+    L = w.limbs
+    p, q, dp, dq, qi = (dev(a) for a in crt_operands(w.keys, w.key_of, L))
+    n = full_operands(w.keys, w.key_of, L, "n")
+    d = full_operands(w.keys, w.key_of, L, "d")
+    e = full_operands(w.keys, w.key_of, L, "e")
+    dec = host(rsagpu.decrypt_crt(dev(w.ctxt), p, q, dp, dq, qi))
+    idx = np.random.default_rng(6).choice(len(w.ctxt), 96, replace=False)
+    assert np.array_equal(dec[idx], oracle_modexp(w.ctxt[idx], d[idx], n[idx]))
+    c = rsagpu.modexp(dev(w.msgs), dev(e), dev(n))
+    assert np.array_equal(host(c)[idx], oracle_modexp(w.msgs[idx], e[idx], n[idx]))
+    m = host(rsagpu.decrypt_crt(c, p, q, dp, dq, qi))
+    assert np.array_equal(m, w.msgs)
+    assert rsagpu.device_errors() == 0
