@@ -18,7 +18,9 @@
  *     asynchronous: the call returns before the results exist.  No entry
  *     point synchronises the device except rsa_device_errors.
  *   - No entry point allocates device memory per call: operands and the
- *     window table of each exponentiation live in registers and LDS.
+ *     window table of each exponentiation live in registers and LDS (the
+ *     only device allocation is an 8-byte error counter made once per
+ *     device, see rsa_init).
  *   - Host-checkable errors are returned before any HIP call.  Per-element
  *     data errors (an even or unit modulus, p <= q for CRT) write 0 to that
  *     element's output and increment a per-device counter that
@@ -104,6 +106,23 @@ typedef struct {
 } rsa_plan;
 
 int rsa_get_plan(int limbs, int kind, rsa_plan *plan);
+
+/*
+ * Overrides the plan of the padded width that `limbs` maps to (kind as in
+ * rsa_get_plan): lanes_per_op must be one of the compiled lane-group sizes
+ * for that width and 2^window_bits operand buffers must fit 64 KiB of LDS.
+ * lanes_per_op = window_bits = 0 restores the default.  Used by the tuner;
+ * affects calls issued afterwards from any thread.  Pure host call.
+ */
+int rsa_set_plan(int limbs, int kind, int lanes_per_op, int window_bits);
+
+/*
+ * Sets up the current device's library state (the data-error counter, one
+ * 8-byte device allocation made once per device).  Every other entry point
+ * does this on first use; call it explicitly before capturing any library
+ * call into a HIP graph.
+ */
+int rsa_init(void);
 
 /*
  * Number of per-element data errors counted on the current device since the

@@ -53,13 +53,70 @@ __device__ __forceinline__ constexpr uint64_t top_lanes_mask()
 }
 
 // ---- cross-lane moves inside a group -----------------------------------
+//
+// Groups of up to 16 lanes never straddle a DPP row, so the moves below are
+// DPP data movements (no LDS round trip): quad_perm for groups of 2 and 4,
+// row shifts with bank masks for 8 and 16.
 
-// Value of lane `src` of this lane's group.
+template <int CTRL, int ROW_MASK = 0xF, int BANK_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+}
+
+enum : int {
+    DPP_QP_0000 = 0x00,      // quad_perm [0,0,0,0]
+    DPP_QP_0022 = 0xA0,      // quad_perm [0,0,2,2]
+    DPP_QP_1230 = 0x39,      // quad_perm [1,2,3,0]
+    DPP_QP_1032 = 0xB1,      // quad_perm [1,0,3,2]
+    DPP_ROW_SHL1 = 0x101,    // lane i <- lane i+1 within a row of 16
+    DPP_ROW_SHR1 = 0x111,    // lane i <- lane i-1 within a row of 16
+    DPP_ROW_SHR4 = 0x114,
+    DPP_ROW_SHR8 = 0x118,
+};
+
+// Value of lane 0 of this lane's group.
+template <int G>
+__device__ __forceinline__ uint32_t grp_bcast0(uint32_t v)
+{
+    if constexpr (G == 1) return v;
+    else if constexpr (G == 2) return dpp<DPP_QP_0022>(0, v);
+    else if constexpr (G == 4) return dpp<DPP_QP_0000>(0, v);
+    else if constexpr (G == 8) {
+        const uint32_t q = dpp<DPP_QP_0000>(0, v);
+        return dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);           // banks 1, 3 take banks 0, 2
+    } else if constexpr (G == 16) {
+        uint32_t q = dpp<DPP_QP_0000>(0, v);
+        q = dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);
+        return dpp<DPP_ROW_SHR8, 0xF, 0xC>(q, q);           // banks 2, 3 take banks 0, 1
+    } else return (uint32_t)__shfl((int)v, 0, G);
+}
+
+// Value of lane `src` of this lane's group (not on hot paths).
 template <int G>
 __device__ __forceinline__ uint32_t grp_bcast(uint32_t v, int src)
 {
     if constexpr (G == 1) return v;
     else return (uint32_t)__shfl((int)v, src, G);
+}
+
+// Lane r receives lane (r+1) mod G of its group.  Used where the group's
+// lane 0 holds zero, so the top lane receives zero (groups of 8 need an
+// explicit zero for the one top lane that a row shift does not reach).
+template <int G>
+__device__ __forceinline__ uint32_t grp_rot_down(uint32_t v)
+{
+    if constexpr (G == 1) return 0;
+    else if constexpr (G == 2) return dpp<DPP_QP_1032>(0, v);
+    else if constexpr (G == 4) return dpp<DPP_QP_1230>(0, v);
+    else if constexpr (G == 8) {
+        const uint32_t u = dpp<DPP_ROW_SHL1>(0, v);
+        return (lane_id() & 7) == 7 ? 0u : u;
+    } else if constexpr (G == 16) return dpp<DPP_ROW_SHL1>(0, v);
+    else {
+        const uint32_t u = (uint32_t)__shfl_down((int)v, 1, G);
+        return (lane_id() & (G - 1)) == G - 1 ? 0u : u;
+    }
 }
 
 // Lane r receives lane r+1's value; the group's top lane receives 0.
@@ -68,8 +125,9 @@ __device__ __forceinline__ uint32_t grp_from_above(uint32_t v)
 {
     if constexpr (G == 1) return 0;
     else {
-        uint32_t u = (uint32_t)__shfl_down((int)v, 1, G);
-        return grp_lane<G>() == G - 1 ? 0u : u;
+        const uint32_t u = (G <= 16) ? dpp<DPP_ROW_SHL1>(0u, v)
+                                     : (uint32_t)__shfl_down((int)v, 1, G);
+        return (lane_id() & (G - 1)) == G - 1 ? 0u : u;
     }
 }
 
@@ -79,8 +137,9 @@ __device__ __forceinline__ uint32_t grp_from_below(uint32_t v)
 {
     if constexpr (G == 1) return 0;
     else {
-        uint32_t u = (uint32_t)__shfl_up((int)v, 1, G);
-        return grp_lane<G>() == 0 ? 0u : u;
+        const uint32_t u = (G <= 16) ? dpp<DPP_ROW_SHR1>(0, v)
+                                     : (uint32_t)__shfl_up((int)v, 1, G);
+        return (lane_id() & (G - 1)) == 0 ? 0u : u;
     }
 }
 
@@ -161,15 +220,43 @@ __device__ __forceinline__ void mac(uint64_t &acc, uint32_t &hi, uint32_t x, uin
         : "vcc");
 }
 
+// Two independent macs; their carries go through two distinct SGPR pairs so
+// the second product issues while the first carry is still in flight.
+__device__ __forceinline__ void mac2(uint64_t &acc0, uint32_t &hi0, uint32_t x0, uint64_t &acc1, uint32_t &hi1,
+                                     uint32_t x1, uint32_t y)
+{
+#ifdef RSAGPU_MAC_VCC
+    mac(acc0, hi0, x0, y);
+    mac(acc1, hi1, x1, y);
+#else
+    uint64_t c0, c1;
+    asm("v_mad_u64_u32 %0, %4, %6, %8, %0\n\t"
+        "v_mad_u64_u32 %1, %5, %7, %8, %1\n\t"
+        "v_addc_co_u32_e64 %2, %4, 0, %2, %4\n\t"
+        "v_addc_co_u32_e64 %3, %5, 0, %3, %5"
+        : "+v"(acc0), "+v"(acc1), "+v"(hi0), "+v"(hi1), "=&s"(c0), "=&s"(c1)
+        : "v"(x0), "v"(x1), "v"(y));
+#endif
+}
+
+// Row update: acc[(j + k) % L] += x[j] * y for all j.
+template <int L>
+__device__ __forceinline__ void mac_row(uint64_t (&acc)[L], uint32_t (&hi)[L], const uint32_t (&x)[L], uint32_t y,
+                                        int k)
+{
+#pragma unroll
+    for (int j = 0; j + 1 < L; j += 2)
+        mac2(acc[(j + k) % L], hi[(j + k) % L], x[j], acc[(j + 1 + k) % L], hi[(j + 1 + k) % L], x[j + 1], y);
+    if constexpr (L % 2 == 1) mac(acc[(L - 1 + k) % L], hi[(L - 1 + k) % L], x[L - 1], y);
+}
+
 // (acc, hi) += x  where x is a 64-bit value at the same weight as acc.
 __device__ __forceinline__ void add96(uint64_t &acc, uint32_t &hi, uint32_t xlo, uint32_t xhi)
 {
-    uint32_t a0 = (uint32_t)acc, a1 = (uint32_t)(acc >> 32);
-    uint64_t t = (uint64_t)a0 + xlo;
-    a0 = (uint32_t)t;
-    t = (uint64_t)a1 + xhi + (uint32_t)(t >> 32);
-    a1 = (uint32_t)t;
-    hi += (uint32_t)(t >> 32);
+    unsigned c0, c1, c2;
+    const uint32_t a0 = __builtin_addc((uint32_t)acc, xlo, 0u, &c0);
+    const uint32_t a1 = __builtin_addc((uint32_t)(acc >> 32), xhi, c0, &c1);
+    hi = __builtin_addc(hi, 0u, c1, &c2);
     acc = ((uint64_t)a1 << 32) | a0;
 }
 
@@ -246,23 +333,17 @@ template <int S, int G>
 __device__ __forceinline__ uint32_t grp_add(uint32_t (&x)[S / G], const uint32_t (&y)[S / G])
 {
     constexpr int L = S / G;
-    uint32_t c = 0;
-    bool allones = true;
+    unsigned c = 0;
+    uint32_t all = 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-        uint64_t t = (uint64_t)x[j] + y[j] + c;
-        x[j] = (uint32_t)t;
-        c = (uint32_t)(t >> 32);
-        allones = allones && (x[j] == 0xFFFFFFFFu);
+        x[j] = __builtin_addc(x[j], y[j], c, &c);
+        all &= x[j];
     }
-    const uint32_t cin = grp_carry_in<G>(c != 0, allones);
-    uint32_t k = cin;
+    const unsigned cin = grp_carry_in<G>(c != 0, all == 0xFFFFFFFFu);
+    unsigned k = cin;
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-        uint64_t t = (uint64_t)x[j] + k;
-        x[j] = (uint32_t)t;
-        k = (uint32_t)(t >> 32);
-    }
+    for (int j = 0; j < L; ++j) x[j] = __builtin_addc(x[j], 0u, k, &k);
     return grp_top_flag<G>((c | k) != 0) ? 1u : 0u;
 }
 
@@ -272,23 +353,17 @@ __device__ __forceinline__ uint32_t grp_sub(uint32_t (&d)[S / G], const uint32_t
                                             const uint32_t (&y)[S / G])
 {
     constexpr int L = S / G;
-    uint32_t b = 0;
-    bool allzero = true;
+    unsigned b = 0;
+    uint32_t any = 0;
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-        uint64_t t = (uint64_t)x[j] - y[j] - b;
-        d[j] = (uint32_t)t;
-        b = (uint32_t)(t >> 32) & 1u;
-        allzero = allzero && (d[j] == 0u);
+        d[j] = __builtin_subc(x[j], y[j], b, &b);
+        any |= d[j];
     }
-    const uint32_t bin = grp_carry_in<G>(b != 0, allzero);
-    uint32_t k = bin;
+    const unsigned bin = grp_carry_in<G>(b != 0, any == 0u);
+    unsigned k = bin;
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-        uint64_t t = (uint64_t)d[j] - k;
-        d[j] = (uint32_t)t;
-        k = (uint32_t)(t >> 32) & 1u;
-    }
+    for (int j = 0; j < L; ++j) d[j] = __builtin_subc(d[j], 0u, k, &k);
     return grp_top_flag<G>((b | k) != 0) ? 1u : 0u;
 }
 
@@ -368,41 +443,31 @@ __device__ __forceinline__ uint32_t grp_normalise(uint32_t (&w)[S / G], const ui
 {
     constexpr int L = S / G;
     static_assert(L >= 2, "at least two limbs per lane");
+    // ripple inside the lane: position j is acc[j] + hi[j] * 2^64
     uint32_t clo = 0, chi = 0;
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-        uint64_t t = (uint64_t)(uint32_t)acc[j] + clo;
-        w[j] = (uint32_t)t;
-        t = (acc[j] >> 32) + (uint64_t)chi + (uint32_t)(t >> 32);
-        clo = (uint32_t)t;
-        chi = hi[j] + (uint32_t)(t >> 32);
+        unsigned c0, c1, c2;
+        w[j] = __builtin_addc((uint32_t)acc[j], clo, 0u, &c0);
+        clo = __builtin_addc((uint32_t)(acc[j] >> 32), chi, c0, &c1);
+        chi = __builtin_addc(hi[j], 0u, c1, &c2);
     }
     // the 64-bit carry of each lane enters the lane above
     const uint32_t rlo = grp_from_below<G>(clo), rhi = grp_from_below<G>(chi);
-    uint32_t own = (grp_lane<G>() == G - 1) ? clo : 0u;   // what leaves the group
-    uint64_t t = (uint64_t)w[0] + rlo;
-    w[0] = (uint32_t)t;
-    t = (uint64_t)w[1] + rhi + (uint32_t)(t >> 32);
-    w[1] = (uint32_t)t;
-    uint32_t k = (uint32_t)(t >> 32);
+    const bool top = grp_lane<G>() == G - 1;
+    unsigned k;
+    w[0] = __builtin_addc(w[0], rlo, 0u, &k);
+    w[1] = __builtin_addc(w[1], rhi, k, &k);
 #pragma unroll
-    for (int j = 2; j < L; ++j) {
-        t = (uint64_t)w[j] + k;
-        w[j] = (uint32_t)t;
-        k = (uint32_t)(t >> 32);
-    }
-    bool allones = true;
+    for (int j = 2; j < L; ++j) w[j] = __builtin_addc(w[j], 0u, k, &k);
+    uint32_t all = 0xFFFFFFFFu;
 #pragma unroll
-    for (int j = 0; j < L; ++j) allones = allones && (w[j] == 0xFFFFFFFFu);
-    const uint32_t cin = grp_carry_in<G>(k != 0, allones);
-    uint32_t k2 = cin;
+    for (int j = 0; j < L; ++j) all &= w[j];
+    unsigned k2 = grp_carry_in<G>(k != 0, all == 0xFFFFFFFFu);
 #pragma unroll
-    for (int j = 0; j < L; ++j) {
-        t = (uint64_t)w[j] + k2;
-        w[j] = (uint32_t)t;
-        k2 = (uint32_t)(t >> 32);
-    }
-    return own + k + k2 + (grp_lane<G>() == G - 1 ? chi : 0u);
+    for (int j = 0; j < L; ++j) w[j] = __builtin_addc(w[j], 0u, k2, &k2);
+    // what leaves the group (meaningful in the top lane)
+    return top ? (clo | chi | k | k2) : 0u;
 }
 
 // ---- Montgomery product -------------------------------------------------
@@ -436,15 +501,14 @@ __device__ __forceinline__ void mont_mul(uint32_t (&r)[S / G], const uint32_t (&
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             // position j of this step lives in register (j + k) % L
-#pragma unroll
-            for (int j = 0; j < L; ++j) mac(acc[(j + k) % L], hi[(j + k) % L], a[j], bv[k]);
+            mac_row<L>(acc, hi, a, bv[k], k);
             const int p0 = k % L, p1 = (k + 1) % L;
-            const uint32_t m = grp_bcast<G>((uint32_t)acc[p0] * n0inv, 0);
-#pragma unroll
-            for (int j = 0; j < L; ++j) mac(acc[(j + k) % L], hi[(j + k) % L], m, n[j]);
+            const uint32_t m = grp_bcast0<G>((uint32_t)acc[p0] * n0inv);
+            mac_row<L>(acc, hi, n, m, k);
             add96(acc[p1], hi[p1], (uint32_t)(acc[p0] >> 32), hi[p0]);
-            const uint32_t in = grp_from_above<G>((uint32_t)acc[p0]);
-            acc[p0] = in;
+            // the bottom word of the group's lane 0 is zero here, so a
+            // rotation inside the group moves zero into the top lane
+            acc[p0] = grp_rot_down<G>((uint32_t)acc[p0]);
             hi[p0] = 0;
         }
     }
@@ -479,8 +543,7 @@ __device__ __forceinline__ void mul_wide(uint32_t (&high)[S / G], const uint32_t
         }
 #pragma unroll
         for (int k = 0; k < L; ++k) {
-#pragma unroll
-            for (int j = 0; j < L; ++j) mac(acc[(j + k) % L], hi[(j + k) % L], a[j], bv[k]);
+            mac_row<L>(acc, hi, a, bv[k], k);
             const int p0 = k % L, p1 = (k + 1) % L;
             sink(i0 + k, (uint32_t)acc[p0]);
             add96(acc[p1], hi[p1], (uint32_t)(acc[p0] >> 32), hi[p0]);

@@ -11,8 +11,6 @@
 
 namespace rsagpu {
 
-extern __device__ unsigned long long g_rsa_errors;
-
 extern __shared__ uint4 rsagpu_lds[];
 
 template <int N>
@@ -216,7 +214,8 @@ template <int S, int G>
 __global__ __launch_bounds__(64) void k_modexp(const uint32_t *__restrict__ base,
                                                const uint32_t *__restrict__ exp,
                                                const uint32_t *__restrict__ mod,
-                                               uint32_t *out, unsigned long long count, int limbs, int w)
+                                               uint32_t *out, unsigned long long count, int limbs, int w,
+                                               unsigned long long *errs)
 {
     constexpr int L = S / G, NG = 64 / G;
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
@@ -240,7 +239,7 @@ __global__ __launch_bounds__(64) void k_modexp(const uint32_t *__restrict__ base
     from_mont<S, G>(A, lds, n, n0inv);
 
     store_limbs<S, G>(out + off, A, limbs, live, valid);
-    if (live && r == 0 && !valid && bl != 1) atomicAdd(&g_rsa_errors, 1ull);
+    if (live && r == 0 && !valid && bl != 1) atomicAdd(errs, 1ull);
 }
 
 // ---- CRT decryption ------------------------------------------------------
@@ -252,7 +251,8 @@ template <int H, int G>
 __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, const uint32_t *__restrict__ p,
                                             const uint32_t *__restrict__ q, const uint32_t *__restrict__ dp,
                                             const uint32_t *__restrict__ dq, const uint32_t *__restrict__ qinv,
-                                            uint32_t *out, unsigned long long count, int hl, int w)
+                                            uint32_t *out, unsigned long long count, int hl, int w,
+                                            unsigned long long *errs)
 {
     constexpr int L = H / G, NG = 64 / G;
     static_assert(NG >= 2, "a wave holds at least one pair of groups");
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
             if (li < full) o[li] = valid ? high[k] : 0u;
         }
     }
-    if (write && r == 0 && !valid) atomicAdd(&g_rsa_errors, 1ull);
+    if (write && r == 0 && !valid) atomicAdd(errs, 1ull);
 }
 
 }  // namespace rsagpu

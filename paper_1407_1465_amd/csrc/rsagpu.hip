@@ -1,90 +1,112 @@
-// Host side of librsagpu.so: argument checks, execution plans and launches.
+// Host side of librsagpu.so: argument checks, execution plans, per-device
+// state and launches.  No arithmetic happens here.
 #include "../../include/rsagpu.h"
-#include "modexp_kernels.hpp"
+#include "launch.hpp"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <mutex>
+
 namespace rsagpu {
 
-__device__ unsigned long long g_rsa_errors = 0;
-
-// Kernel widths (limbs) with their lanes per exponentiation (G) and window.
-struct PlanRow {
+struct Instance {
     int S;
+    int G;
+    modexp_launcher modexp;
+    crt_launcher crt;
+};
+
+static const Instance kInstances[] = {
+#define X(S_, G_) {S_, G_, &launch_modexp<S_, G_>, &launch_crt<S_, G_>},
+#include "instances.def"
+#undef X
+};
+
+static const int kWidths[] = {2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+static const int kNumWidths = sizeof(kWidths) / sizeof(kWidths[0]);
+
+// Default plan per padded width: lanes per exponentiation G (limbs per lane
+// L = S / G) and window bits w.  kind 0 = plain exponentiation, kind 1 = CRT
+// half.  L stays near 8 so the per-step cross-lane work is amortised over 2L
+// products, and the window is the largest whose 2^w operand buffers per wave
+// (2^w * 256 * L bytes of LDS) still let 8 waves share a CU's 160 KiB: with
+// fewer resident waves the dependency chain of each Montgomery step (product,
+// m, broadcast, products) is no longer hidden, which costs far more than the
+// extra multiplications of a narrower window.
+struct Plan {
     int G;
     int w;
 };
-
-// One row per supported padded width: limbs per lane L = S / G stays at 6..16
-// so that the per-step cross-lane work is amortised over 2L products, and the
-// window is the largest whose LDS table (2^w operand buffers of 64*L words)
-// keeps several waves resident per CU.
-static const PlanRow kPlans[] = {
-    {2, 1, 4},   {4, 1, 4},   {8, 1, 4},   {12, 2, 4},  {16, 2, 4},  {24, 4, 4},
-    {32, 4, 4},  {48, 4, 3},  {64, 8, 4},  {96, 8, 3},  {128, 16, 4},
+static const Plan kDefault[2][kNumWidths] = {
+    {{1, 4}, {1, 4}, {1, 3}, {2, 3}, {2, 3}, {4, 3}, {4, 3}, {4, 3}, {8, 3}, {8, 3}, {16, 3}},
+    {{1, 4}, {1, 4}, {1, 3}, {2, 3}, {2, 3}, {4, 3}, {4, 3}, {4, 3}, {8, 3}, {8, 3}, {16, 3}},
 };
 
-static const PlanRow *plan_for(int limbs)
+// Current plans (packed G << 8 | w); overridable with rsa_set_plan.
+static std::atomic<int> g_plan[2][kNumWidths];
+static std::once_flag g_plan_once;
+
+static void init_plans()
 {
-    for (const PlanRow &p : kPlans)
-        if (p.S >= limbs) return &p;
+    for (int k = 0; k < 2; ++k)
+        for (int i = 0; i < kNumWidths; ++i) g_plan[k][i].store(kDefault[k][i].G << 8 | kDefault[k][i].w);
+}
+
+static int width_index(int limbs)
+{
+    for (int i = 0; i < kNumWidths; ++i)
+        if (kWidths[i] >= limbs) return i;
+    return -1;
+}
+
+static const Instance *find_instance(int S, int G)
+{
+    for (const Instance &in : kInstances)
+        if (in.S == S && in.G == G) return &in;
     return nullptr;
 }
 
-static size_t lds_bytes(const PlanRow &p)
+struct Resolved {
+    const Instance *inst;
+    int w;
+};
+
+static bool resolve(int limbs, int kind, Resolved *r)
 {
-    // operand buffer + table entries 1 .. 2^w - 1, each S * (64 / G) words
-    return (size_t)(1u << p.w) * (size_t)p.S * (size_t)(64 / p.G) * 4u;
+    std::call_once(g_plan_once, init_plans);
+    const int i = width_index(limbs);
+    if (i < 0) return false;
+    const int packed = g_plan[kind][i].load();
+    r->inst = find_instance(kWidths[i], packed >> 8);
+    r->w = packed & 0xFF;
+    return r->inst != nullptr;
 }
 
-template <int S, int G>
-static hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32_t *mod, uint32_t *out,
-                                size_t count, int limbs, int w, hipStream_t stream)
-{
-    const size_t ng = 64 / G;
-    const size_t blocks = (count + ng - 1) / ng;
-    const size_t lds = (size_t)(1u << w) * (size_t)S * ng * 4u;
-    hipLaunchKernelGGL((k_modexp<S, G>), dim3((unsigned)blocks), dim3(64), lds, stream, base, exp, mod, out,
-                       (unsigned long long)count, limbs, w);
-    return hipGetLastError();
-}
+// ---- per-device state: the data-error counter ------------------------------
 
-template <int H, int G>
-static hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
-                             const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count, int hl, int w,
-                             hipStream_t stream)
-{
-    const size_t pairs = 64 / G / 2;
-    const size_t blocks = (count + pairs - 1) / pairs;
-    const size_t lds = (size_t)(1u << w) * (size_t)H * (64 / G) * 4u;
-    hipLaunchKernelGGL((k_crt<H, G>), dim3((unsigned)blocks), dim3(64), lds, stream, c, p, q, dp, dq, qinv, out,
-                       (unsigned long long)count, hl, w);
-    return hipGetLastError();
-}
+static const int kMaxDevices = 64;
+static unsigned long long *g_errs[kMaxDevices];
+static std::mutex g_dev_mutex;
 
-#define RSAGPU_FOR_EACH_PLAN(X) \
-    X(2, 1) X(4, 1) X(8, 1) X(12, 2) X(16, 2) X(24, 4) X(32, 4) X(48, 4) X(64, 8) X(96, 8) X(128, 16)
-
-static hipError_t dispatch_modexp(const PlanRow &pl, const uint32_t *base, const uint32_t *exp,
-                                  const uint32_t *mod, uint32_t *out, size_t count, int limbs, hipStream_t s)
+static int device_state(unsigned long long **errs)
 {
-#define X(S_, G_) \
-    if (pl.S == S_ && pl.G == G_) return launch_modexp<S_, G_>(base, exp, mod, out, count, limbs, pl.w, s);
-    RSAGPU_FOR_EACH_PLAN(X)
-#undef X
-    return hipErrorInvalidValue;
-}
-
-static hipError_t dispatch_crt(const PlanRow &pl, const uint32_t *c, const uint32_t *p, const uint32_t *q,
-                               const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv, uint32_t *out,
-                               size_t count, int hl, hipStream_t s)
-{
-#define X(S_, G_) \
-    if (pl.S == S_ && pl.G == G_) return launch_crt<S_, G_>(c, p, q, dp, dq, qinv, out, count, hl, pl.w, s);
-    RSAGPU_FOR_EACH_PLAN(X)
-#undef X
-    return hipErrorInvalidValue;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RSA_EHIP;
+    std::lock_guard<std::mutex> lock(g_dev_mutex);
+    if (!g_errs[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, sizeof(unsigned long long));
+        if (e != hipSuccess) return e == hipErrorOutOfMemory ? RSA_ENOMEM : RSA_EHIP;
+        e = hipMemset(p, 0, sizeof(unsigned long long));
+        if (e != hipSuccess) return RSA_EHIP;
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return RSA_EHIP;
+        g_errs[dev] = static_cast<unsigned long long *>(p);
+    }
+    *errs = g_errs[dev];
+    return RSA_OK;
 }
 
 static int status_of(hipError_t e)
@@ -98,16 +120,25 @@ static int status_of(hipError_t e)
 
 using namespace rsagpu;
 
+extern "C" int rsa_init(void)
+{
+    unsigned long long *errs = nullptr;
+    return device_state(&errs);
+}
+
 extern "C" int rsa_modexp_batch(const uint32_t *base, const uint32_t *exp, const uint32_t *mod, uint32_t *out,
                                 size_t count, int limbs, hipStream_t stream)
 {
     if (limbs < 1 || limbs > RSA_MAX_LIMBS) return RSA_ELIMBS;
     if (count == 0) return RSA_OK;
     if (!base || !exp || !mod || !out) return RSA_EINVAL;
-    const PlanRow *pl = plan_for(limbs);
-    if (!pl) return RSA_ELIMBS;
-    if ((count + 64 / pl->G - 1) / (64 / pl->G) > 0x7FFFFFFFull) return RSA_EINVAL;
-    return status_of(dispatch_modexp(*pl, base, exp, mod, out, count, limbs, stream));
+    Resolved r;
+    if (!resolve(limbs, 0, &r)) return RSA_ELIMBS;
+    if ((count + 64 / r.inst->G - 1) / (64 / r.inst->G) > 0x7FFFFFFFull) return RSA_EINVAL;
+    unsigned long long *errs = nullptr;
+    const int st = device_state(&errs);
+    if (st != RSA_OK) return st;
+    return status_of(r.inst->modexp(base, exp, mod, out, count, limbs, r.w, errs, stream));
 }
 
 extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
@@ -117,36 +148,62 @@ extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const
     if (limbs < 2 || limbs > RSA_MAX_LIMBS || (limbs & 1)) return RSA_ELIMBS;
     if (count == 0) return RSA_OK;
     if (!c || !p || !q || !dp || !dq || !qinv || !out) return RSA_EINVAL;
-    const PlanRow *pl = plan_for(limbs / 2);
-    if (!pl) return RSA_ELIMBS;
-    if (pl->G > 32) return RSA_ELIMBS;
-    if ((count + 32 / pl->G - 1) / (32 / pl->G) > 0x7FFFFFFFull) return RSA_EINVAL;
-    return status_of(dispatch_crt(*pl, c, p, q, dp, dq, qinv, out, count, limbs / 2, stream));
+    Resolved r;
+    if (!resolve(limbs / 2, 1, &r)) return RSA_ELIMBS;
+    const size_t pairs = 32 / r.inst->G;
+    if ((count + pairs - 1) / pairs > 0x7FFFFFFFull) return RSA_EINVAL;
+    unsigned long long *errs = nullptr;
+    const int st = device_state(&errs);
+    if (st != RSA_OK) return st;
+    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, out, count, limbs / 2, r.w, errs, stream));
 }
 
 extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)
 {
     if (!plan || (kind != 0 && kind != 1)) return RSA_EINVAL;
     if (limbs < 1 || limbs > RSA_MAX_LIMBS) return RSA_ELIMBS;
-    const PlanRow *pl = plan_for(limbs);
-    if (!pl) return RSA_ELIMBS;
-    plan->padded_limbs = pl->S;
-    plan->lanes_per_op = pl->G;
-    plan->limbs_per_lane = pl->S / pl->G;
-    plan->window_bits = pl->w;
-    plan->lds_bytes = (int)lds_bytes(*pl);
+    Resolved r;
+    if (!resolve(limbs, kind, &r)) return RSA_ELIMBS;
+    plan->padded_limbs = r.inst->S;
+    plan->lanes_per_op = r.inst->G;
+    plan->limbs_per_lane = r.inst->S / r.inst->G;
+    plan->window_bits = r.w;
+    plan->lds_bytes = (int)lds_bytes_for(r.inst->S, r.inst->G, r.w);
+    return RSA_OK;
+}
+
+extern "C" int rsa_set_plan(int limbs, int kind, int lanes_per_op, int window_bits)
+{
+    if (kind != 0 && kind != 1) return RSA_EINVAL;
+    if (limbs < 1 || limbs > RSA_MAX_LIMBS) return RSA_ELIMBS;
+    std::call_once(g_plan_once, init_plans);
+    const int i = width_index(limbs);
+    if (i < 0) return RSA_ELIMBS;
+    if (lanes_per_op == 0 && window_bits == 0) {           // back to the default
+        g_plan[kind][i].store(kDefault[kind][i].G << 8 | kDefault[kind][i].w);
+        return RSA_OK;
+    }
+    if (!find_instance(kWidths[i], lanes_per_op)) return RSA_EINVAL;
+    if (window_bits < 1 || window_bits > 7) return RSA_EINVAL;
+    if (lds_bytes_for(kWidths[i], lanes_per_op, window_bits) > 64 * 1024) return RSA_EINVAL;
+    g_plan[kind][i].store(lanes_per_op << 8 | window_bits);
     return RSA_OK;
 }
 
 extern "C" int rsa_device_errors(hipStream_t stream, uint64_t *n_bad)
 {
     if (!n_bad) return RSA_EINVAL;
+    unsigned long long *errs = nullptr;
+    int st = device_state(&errs);
+    if (st != RSA_OK) return st;
     hipError_t e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return status_of(e);
-    unsigned long long v = 0, zero = 0;
-    e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_rsa_errors), sizeof(v), 0, hipMemcpyDeviceToHost);
+    unsigned long long v = 0;
+    e = hipMemcpy(&v, errs, sizeof(v), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return status_of(e);
-    e = hipMemcpyToSymbol(HIP_SYMBOL(g_rsa_errors), &zero, sizeof(zero), 0, hipMemcpyHostToDevice);
+    e = hipMemset(errs, 0, sizeof(v));
+    if (e != hipSuccess) return status_of(e);
+    e = hipDeviceSynchronize();
     if (e != hipSuccess) return status_of(e);
     *n_bad = v;
     return RSA_OK;
@@ -165,4 +222,4 @@ extern "C" const char *rsa_status_str(int status)
     }
 }
 
-extern "C" int rsa_version(void) { return 100; }
+extern "C" int rsa_version(void) { return 10000 + 100 * 1; }

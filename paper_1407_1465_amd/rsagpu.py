@@ -44,10 +44,14 @@ class _Plan(ctypes.Structure):
 
 _lib.rsa_get_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Plan)]
 _lib.rsa_get_plan.restype = ctypes.c_int
+_lib.rsa_set_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+_lib.rsa_set_plan.restype = ctypes.c_int
+_lib.rsa_init.argtypes = []
+_lib.rsa_init.restype = ctypes.c_int
 
 # exported symbols, in the order include/rsagpu.h declares them
-EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_get_plan", "rsa_device_errors",
-           "rsa_status_str", "rsa_version")
+EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_get_plan", "rsa_set_plan", "rsa_init",
+           "rsa_device_errors", "rsa_status_str", "rsa_version")
 
 
 class RSAError(RuntimeError):
@@ -74,6 +78,15 @@ def get_plan(limbs: int, kind: int = 0) -> Plan:
     p = _Plan()
     _check(_lib.rsa_get_plan(limbs, kind, ctypes.byref(p)), "rsa_get_plan")
     return Plan(p.padded_limbs, p.lanes_per_op, p.limbs_per_lane, p.window_bits, p.lds_bytes)
+
+
+def set_plan(limbs: int, kind: int, lanes_per_op: int, window_bits: int) -> None:
+    """Override the plan of a limb width (0, 0 restores the default)."""
+    _check(_lib.rsa_set_plan(limbs, kind, lanes_per_op, window_bits), "rsa_set_plan")
+
+
+def init() -> None:
+    _check(_lib.rsa_init(), "rsa_init")
 
 
 def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
