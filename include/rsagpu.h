@@ -91,13 +91,17 @@ int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *
                           uint32_t *out, size_t count, int limbs, hipStream_t stream);
 
 /*
- * Execution plan used for a limb width: lanes per exponentiation (G), limbs
- * per lane (limbs_per_lane = padded_limbs / G), fixed-window width (bits of
- * exponent per table lookup, paper Section 3.6.4), the padded limb width the
- * kernel runs at, and the LDS bytes per 64-lane workgroup.  kind: 0 = plain
- * exponentiation, 1 = CRT half (modulus of `limbs` limbs).  Pure host query.
+ * Execution plan used for a limb width: the limb radix the kernel computes
+ * in (radix_bits = 32, or 29 for the reduced-radix kernels whose 64-bit
+ * accumulators need no carry handling), the kernel's limb count in that
+ * radix (padded_limbs), lanes per exponentiation (G), limbs per lane
+ * (padded_limbs / G), fixed-window width (bits of exponent per table lookup,
+ * paper Section 3.6.4) and the LDS bytes per 64-lane workgroup.
+ * kind: 0 = plain exponentiation, 1 = CRT half (modulus of `limbs` limbs).
+ * Inputs and outputs are 32-bit limbs whatever the radix.  Pure host query.
  */
 typedef struct {
+    int radix_bits;
     int padded_limbs;
     int lanes_per_op;
     int limbs_per_lane;
@@ -108,13 +112,14 @@ typedef struct {
 int rsa_get_plan(int limbs, int kind, rsa_plan *plan);
 
 /*
- * Overrides the plan of the padded width that `limbs` maps to (kind as in
- * rsa_get_plan): lanes_per_op must be one of the compiled lane-group sizes
- * for that width and 2^window_bits operand buffers must fit 64 KiB of LDS.
- * lanes_per_op = window_bits = 0 restores the default.  Used by the tuner;
- * affects calls issued afterwards from any thread.  Pure host call.
+ * Overrides the plan of the width class that `limbs` maps to (kind as in
+ * rsa_get_plan): (radix_bits, lanes_per_op) must name a compiled kernel
+ * instance for that class, 2 <= window_bits <= 7, and 2^window_bits operand
+ * buffers must fit 64 KiB of LDS.  All three zero restores the default.
+ * Used by the tuner; affects calls issued afterwards from any thread.
+ * Pure host call.
  */
-int rsa_set_plan(int limbs, int kind, int lanes_per_op, int window_bits);
+int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int window_bits);
 
 /*
  * Sets up the current device's library state (the data-error counter, one

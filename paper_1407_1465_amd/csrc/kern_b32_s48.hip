@@ -1,0 +1,6 @@
+// Kernel instances: radix 2^32, 48 limbs; lanes per exponentiation 4, 8, 16.
+#include "launch_impl.hpp"
+
+RSAGPU_INSTANTIATE(32, 48, 4)
+RSAGPU_INSTANTIATE(32, 48, 8)
+RSAGPU_INSTANTIATE(32, 48, 16)

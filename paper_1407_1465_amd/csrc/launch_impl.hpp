@@ -6,36 +6,36 @@
 
 namespace rsagpu {
 
-template <int S, int G>
+template <int S, int G, int B>
 hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32_t *mod, uint32_t *out,
                          size_t count, int limbs, int w, unsigned long long *errs, hipStream_t stream)
 {
     const size_t ng = 64 / G;
     const size_t blocks = (count + ng - 1) / ng;
-    hipLaunchKernelGGL((k_modexp<S, G>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(S, G, w), stream, base,
+    hipLaunchKernelGGL((k_modexp<S, G, B>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(S, G, w), stream, base,
                        exp, mod, out, (unsigned long long)count, limbs, w, errs);
     return hipGetLastError();
 }
 
-template <int H, int G>
+template <int H, int G, int B>
 hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
                       const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count, int hl, int w,
                       unsigned long long *errs, hipStream_t stream)
 {
     const size_t pairs = 64 / G / 2;
     const size_t blocks = (count + pairs - 1) / pairs;
-    hipLaunchKernelGGL((k_crt<H, G>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(H, G, w), stream, c, p, q,
+    hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(H, G, w), stream, c, p, q,
                        dp, dq, qinv, out, (unsigned long long)count, hl, w, errs);
     return hipGetLastError();
 }
 
 }  // namespace rsagpu
 
-#define RSAGPU_INSTANTIATE(S_, G_)                                                                          \
-    template hipError_t rsagpu::launch_modexp<S_, G_>(const uint32_t *, const uint32_t *, const uint32_t *, \
+#define RSAGPU_INSTANTIATE(B_, S_, G_)                                                                      \
+    template hipError_t rsagpu::launch_modexp<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *, \
                                                       uint32_t *, size_t, int, int, unsigned long long *,   \
                                                       hipStream_t);                                         \
-    template hipError_t rsagpu::launch_crt<S_, G_>(const uint32_t *, const uint32_t *, const uint32_t *,    \
+    template hipError_t rsagpu::launch_crt<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *,    \
                                                    const uint32_t *, const uint32_t *, const uint32_t *,    \
                                                    uint32_t *, size_t, int, int, unsigned long long *,      \
                                                    hipStream_t);

@@ -5,65 +5,129 @@
 // the next Montgomery product) and the fixed-window table T[1 .. 2^w - 1],
 // each entry one S-limb integer per group (paper, Section 3.6.4: left-to-right
 // k-ary exponentiation with a precomputed table of the powers g^1 .. g^(2^k-1)).
+//
+// The kernels are generic over the limb radix 2^B: B = 32 uses the carry-
+// tracking arithmetic of group_bn.hpp, B < 32 the carry-free accumulation of
+// radix_bn.hpp.  Inputs and outputs are always 32-bit-limb integers.
 #pragma once
 
 #include "group_bn.hpp"
+#include "radix_bn.hpp"
 
 namespace rsagpu {
 
 extern __shared__ uint4 rsagpu_lds[];
 
-template <int N>
-struct OddPart { static constexpr int value = (N % 2 == 0) ? OddPart<N / 2>::value : N; };
-template <>
-struct OddPart<0> { static constexpr int value = 1; };
+// Arithmetic of one lane group in radix 2^B.
+template <int S, int G, int B>
+struct Arith {
+    static constexpr int L = S / G;
+    static __device__ __forceinline__ uint32_t n0inv(uint32_t n0) { return neg_inv32(n0) & Radix<B>::MASK; }
+    static __device__ __forceinline__ void load(uint32_t (&x)[L], const uint32_t *p, int nwords, int bitoff,
+                                                bool live)
+    {
+        rload<S, G, B>(x, p, nwords, bitoff, live);
+    }
+    static __device__ __forceinline__ void mont_mul(uint32_t (&r)[L], const uint32_t (&a)[L], const uint32_t *b,
+                                                    const uint32_t (&n)[L], uint32_t n0inv)
+    {
+        rmont_mul<S, G, B>(r, a, b, n, n0inv);
+    }
+    template <typename Sink>
+    static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
+                                                    const uint32_t (&a)[L], const uint32_t *b, Sink sink)
+    {
+        rmul_wide<S, G, B>(hi, init, a, b, sink);
+    }
+    static __device__ __forceinline__ uint32_t add(uint32_t (&x)[L], const uint32_t (&y)[L])
+    {
+        return rgrp_add<S, G, B>(x, y);
+    }
+    static __device__ __forceinline__ uint32_t sub(uint32_t (&d)[L], const uint32_t (&x)[L], const uint32_t (&y)[L])
+    {
+        return rgrp_sub<S, G, B>(d, x, y);
+    }
+    static __device__ __forceinline__ void cond_sub(uint32_t (&x)[L], uint32_t top, const uint32_t (&n)[L])
+    {
+        rgrp_cond_sub<S, G, B>(x, top, n);
+    }
+    static __device__ __forceinline__ void dbl_mod(uint32_t (&x)[L], const uint32_t (&n)[L])
+    {
+        rgrp_dbl_mod<S, G, B>(x, n);
+    }
+    static __device__ __forceinline__ uint32_t bitlen(const uint32_t (&x)[L]) { return rgrp_bitlen<S, G, B>(x); }
+};
 
-template <int N>
-struct Log2 { static constexpr int value = 1 + Log2<N / 2>::value; };
-template <>
-struct Log2<1> { static constexpr int value = 0; };
-
-// Loads limbs [r*L, r*L + L) of a `limbs`-limb integer at p (zero beyond
-// `limbs`, zero when !live).
 template <int S, int G>
-__device__ __forceinline__ void load_limbs(uint32_t (&x)[S / G], const uint32_t *p, int limbs, bool live)
+struct Arith<S, G, 32> {
+    static constexpr int L = S / G;
+    static __device__ __forceinline__ uint32_t n0inv(uint32_t n0) { return neg_inv32(n0); }
+    static __device__ __forceinline__ void load(uint32_t (&x)[L], const uint32_t *p, int nwords, int bitoff,
+                                                bool live)
+    {
+        const int r = grp_lane<G>(), w0 = bitoff >> 5;
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const int w = w0 + r * L + k;
+            x[k] = (live && w < nwords) ? p[w] : 0u;
+        }
+    }
+    static __device__ __forceinline__ void mont_mul(uint32_t (&r)[L], const uint32_t (&a)[L], const uint32_t *b,
+                                                    const uint32_t (&n)[L], uint32_t n0inv)
+    {
+        rsagpu::mont_mul<S, G>(r, a, b, n, n0inv);
+    }
+    template <typename Sink>
+    static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
+                                                    const uint32_t (&a)[L], const uint32_t *b, Sink sink)
+    {
+        rsagpu::mul_wide<S, G>(hi, init, a, b, sink);
+    }
+    static __device__ __forceinline__ uint32_t add(uint32_t (&x)[L], const uint32_t (&y)[L])
+    {
+        return grp_add<S, G>(x, y);
+    }
+    static __device__ __forceinline__ uint32_t sub(uint32_t (&d)[L], const uint32_t (&x)[L], const uint32_t (&y)[L])
+    {
+        return grp_sub<S, G>(d, x, y);
+    }
+    static __device__ __forceinline__ void cond_sub(uint32_t (&x)[L], uint32_t top, const uint32_t (&n)[L])
+    {
+        grp_cond_sub<S, G>(x, top, n);
+    }
+    static __device__ __forceinline__ void dbl_mod(uint32_t (&x)[L], const uint32_t (&n)[L]) { grp_dbl_mod<S, G>(x, n); }
+    static __device__ __forceinline__ uint32_t bitlen(const uint32_t (&x)[L]) { return grp_bitlen<S, G>(x); }
+};
+
+// Writes the group's S-limb integer x (radix 2^B) as `nwords` 32-bit words at
+// p (only when live; zeros when !valid).  For B < 32 the limbs go through the
+// group's slot of the LDS staging area `stage` (S words per group).
+template <int S, int G, int B>
+__device__ __forceinline__ void store_words(uint32_t *p, const uint32_t (&x)[S / G], int nwords, bool live,
+                                            bool valid, uint32_t *stage)
 {
     constexpr int L = S / G;
-    const int r = grp_lane<G>();
+    const int r = grp_lane<G>(), g = grp_index<G>();
+    if constexpr (B == 32) {
+        if (!live) return;
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const int li = r * L + k;
-        x[k] = (live && li < limbs) ? p[li] : 0u;
-    }
-}
-
-template <int S, int G>
-__device__ __forceinline__ void store_limbs(uint32_t *p, const uint32_t (&x)[S / G], int limbs, bool live,
-                                            bool valid)
-{
-    constexpr int L = S / G;
-    const int r = grp_lane<G>();
-    if (!live) return;
+        for (int k = 0; k < L; ++k) {
+            const int w = r * L + k;
+            if (w < nwords) p[w] = valid ? x[k] : 0u;
+        }
+    } else {
+        uint32_t *q = stage + g * S;
+        lds_sync();
 #pragma unroll
-    for (int k = 0; k < L; ++k) {
-        const int li = r * L + k;
-        if (li < limbs) p[li] = valid ? x[k] : 0u;
+        for (int k = 0; k < L; ++k) q[r * L + k] = x[k];
+        lds_sync();
+        if (live)
+            for (int w = r; w < nwords; w += G) p[w] = valid ? rword<B>(q, S, w) : 0u;
     }
-}
-
-// One Montgomery squaring of A through the operand buffer.
-template <int S, int G>
-__device__ __forceinline__ void mont_sqr_lds(uint32_t (&A)[S / G], uint32_t *abuf, const uint32_t (&n)[S / G],
-                                             uint32_t n0inv)
-{
-    lds_sync();
-    lds_put<S, G>(abuf, A);
-    lds_sync();
-    mont_mul<S, G>(A, A, abuf, n, n0inv);
 }
 
 // r = a * c * R^-1 mod n with c (registers) staged through the operand buffer.
-template <int S, int G>
+template <int S, int G, int B>
 __device__ __forceinline__ void mont_mul_reg(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
                                              const uint32_t (&c)[S / G], uint32_t *abuf,
                                              const uint32_t (&n)[S / G], uint32_t n0inv)
@@ -71,20 +135,32 @@ __device__ __forceinline__ void mont_mul_reg(uint32_t (&r)[S / G], const uint32_
     lds_sync();
     lds_put<S, G>(abuf, c);
     lds_sync();
-    mont_mul<S, G>(r, a, abuf, n, n0inv);
+    Arith<S, G, B>::mont_mul(r, a, abuf, n, n0inv);
 }
 
-// Montgomery constants of an odd modulus n > 1, R = 2^(32S):
-//   one = R mod n          (2^(bitlen(n)-1) doubled 32S - bitlen(n) + 1 times)
-//   r2  = R^2 mod n        (one doubled c times, then squared j times in
-//                           Montgomery form, where c * 2^j = 32S)
-template <int S, int G>
+// A = A^2 * R^-1 mod n through the operand buffer.
+template <int S, int G, int B>
+__device__ __forceinline__ void mont_sqr(uint32_t (&A)[S / G], uint32_t *abuf, const uint32_t (&n)[S / G],
+                                         uint32_t n0inv)
+{
+    mont_mul_reg<S, G, B>(A, A, A, abuf, n, n0inv);
+}
+
+// Montgomery constants of an odd modulus n > 1 in radix 2^B, R = 2^(B*S):
+//   one = R mod n:   2^(bitlen(n)-1) doubled B*S - bitlen(n) + 1 times;
+//   r2 = R^2 mod n:  X = 2R mod n, then left-to-right over the bits of B*S
+//                    below the top one: X <- X*X/R (exponent of 2 doubles),
+//                    and X <- X*(2R)/R when the bit is set (exponent + 1);
+//                    X = R * 2^e mod n throughout, ending at e = B*S.
+// `aux` is an LDS operand buffer other than `abuf`.
+template <int S, int G, int B>
 __device__ __forceinline__ void mont_setup(uint32_t (&one)[S / G], uint32_t (&r2)[S / G],
                                            const uint32_t (&n)[S / G], uint32_t n0inv, bool valid,
-                                           uint32_t *abuf)
+                                           uint32_t *abuf, uint32_t *aux)
 {
+    using A = Arith<S, G, B>;
     constexpr int L = S / G;
-    const uint32_t bl = grp_bitlen<S, G>(n);
+    const uint32_t bl = A::bitlen(n);
     const int r = grp_lane<G>();
 #pragma unroll
     for (int k = 0; k < L; ++k) one[k] = 0;
@@ -92,26 +168,33 @@ __device__ __forceinline__ void mont_setup(uint32_t (&one)[S / G], uint32_t (&r2
         const int top = (int)bl - 1;
 #pragma unroll
         for (int k = 0; k < L; ++k)
-            if (r * L + k == top / 32) one[k] = 1u << (top % 32);
+            if (r * L + k == top / B) one[k] = 1u << (top % B);
     }
-    const uint32_t ndbl = valid ? (uint32_t)(32 * S) - bl + 1 : 0u;
+    const uint32_t ndbl = valid ? (uint32_t)(B * S) - bl + 1 : 0u;
     const uint32_t maxd = wave_max(ndbl);
     for (uint32_t t = 0; t < maxd; ++t) {
         uint32_t y[L];
 #pragma unroll
         for (int k = 0; k < L; ++k) y[k] = one[k];
-        grp_dbl_mod<S, G>(y, n);
+        A::dbl_mod(y, n);
         const bool act = t < ndbl;
 #pragma unroll
         for (int k = 0; k < L; ++k) one[k] = act ? y[k] : one[k];
     }
-    constexpr int C = OddPart<S>::value;
-    constexpr int J = Log2<(32 * S) / C>::value;
-    static_assert(C * (1 << J) == 32 * S, "c * 2^j must be 32S");
+    uint32_t x2[L];
 #pragma unroll
-    for (int k = 0; k < L; ++k) r2[k] = one[k];
-    for (int t = 0; t < C; ++t) grp_dbl_mod<S, G>(r2, n);
-    for (int t = 0; t < J; ++t) mont_sqr_lds<S, G>(r2, abuf, n, n0inv);
+    for (int k = 0; k < L; ++k) x2[k] = one[k];
+    A::dbl_mod(x2, n);                                   // 2R mod n
+    lds_sync();
+    lds_put<S, G>(aux, x2);
+#pragma unroll
+    for (int k = 0; k < L; ++k) r2[k] = x2[k];
+    constexpr int E = B * S;
+    constexpr int TOP = 31 - __builtin_clz((unsigned)E);
+    for (int bit = TOP - 1; bit >= 0; --bit) {
+        mont_sqr<S, G, B>(r2, abuf, n, n0inv);
+        if ((E >> bit) & 1) A::mont_mul(r2, r2, aux, n, n0inv);
+    }
 }
 
 // Fixed-window digit of an exponent: bits [pos, pos + w) (zero beyond elimbs).
@@ -124,8 +207,8 @@ __device__ __forceinline__ uint32_t exp_digit(const uint32_t *ep, int elimbs, in
     return (uint32_t)v & ((1u << w) - 1u);
 }
 
-// A = x^e mod n, returned in Montgomery form, for xt = x*R mod n in Montgomery
-// form and exponent e of elimbs limbs at ep (read only when use_exp).
+// A = x^e mod n in Montgomery form, for xt = x*R mod n and an exponent e of
+// elimbs 32-bit words at ep (read only when use_exp).
 //
 // Left-to-right k-ary method (Section 3.6.4, Fig. 6) with k = w: table
 // T[i] = x^i (i = 1 .. 2^w - 1) in LDS, then, from the most significant
@@ -134,18 +217,18 @@ __device__ __forceinline__ uint32_t exp_digit(const uint32_t *ep, int elimbs, in
 // digit skips its product.  The window count is the wave's largest exponent
 // length, so groups with shorter exponents run on A = 1 until their digits
 // start.
-template <int S, int G>
+template <int S, int G, int B>
 __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
                                              const uint32_t *ep, int elimbs, bool use_exp,
                                              const uint32_t (&n)[S / G], uint32_t n0inv,
                                              const uint32_t (&one)[S / G], uint32_t *lds, int w)
 {
     using Ly = Layout<S, G>;
+    using Ar = Arith<S, G, B>;
     constexpr int L = Ly::L;
     uint32_t *abuf = lds;
     uint32_t *tbl = lds + Ly::WORDS;            // entry i at tbl + (i - 1) * WORDS
     const int g = grp_index<G>();
-    const int r = grp_lane<G>();
 
     // table T[1] = x, T[i] = T[i-1] * x
     lds_sync();
@@ -156,17 +239,19 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     lds_sync();
     const int tsize = 1 << w;
     for (int i = 2; i < tsize; ++i) {
-        mont_mul<S, G>(cur, cur, tbl, n, n0inv);
+        Ar::mont_mul(cur, cur, tbl, n, n0inv);
         lds_put<S, G>(tbl + (i - 1) * Ly::WORDS, cur);
     }
     lds_sync();
 
-    // exponent length, maximised over the wave
+    // exponent length in bits, maximised over the wave (the group's lanes
+    // share the exponent words; each lane scans a slice)
     uint32_t ebits = 0;
     if (use_exp) {
-#pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const int li = r * L + k;
+        const int per = (elimbs + G - 1) / G;
+        const int r = grp_lane<G>();
+        for (int k = 0; k < per; ++k) {
+            const int li = r * per + k;
             const uint32_t v = li < elimbs ? ep[li] : 0u;
             if (v) ebits = (uint32_t)(32 * li + 32 - __clz(v));
         }
@@ -187,10 +272,10 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     }
     for (int win = nwin - 2; win >= 0; --win) {
         d = use_exp ? exp_digit(ep, elimbs, win * w, w) : 0u;
-        for (int s = 0; s < w; ++s) mont_sqr_lds<S, G>(A, abuf, n, n0inv);
+        for (int s = 0; s < w; ++s) mont_sqr<S, G, B>(A, abuf, n, n0inv);
         if (__ballot(d != 0u)) {
             uint32_t t[L];
-            mont_mul<S, G>(t, A, tbl + ((d ? d : 1u) - 1) * Ly::WORDS, n, n0inv);
+            Ar::mont_mul(t, A, tbl + ((d ? d : 1u) - 1) * Ly::WORDS, n, n0inv);
 #pragma unroll
             for (int k = 0; k < L; ++k) A[k] = d ? t[k] : A[k];
         }
@@ -198,7 +283,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
 }
 
 // A = A * R^-1 mod n (leave Montgomery form).
-template <int S, int G>
+template <int S, int G, int B>
 __device__ __forceinline__ void from_mont(uint32_t (&A)[S / G], uint32_t *abuf, const uint32_t (&n)[S / G],
                                           uint32_t n0inv)
 {
@@ -206,17 +291,21 @@ __device__ __forceinline__ void from_mont(uint32_t (&A)[S / G], uint32_t *abuf, 
     uint32_t u[L];
 #pragma unroll
     for (int k = 0; k < L; ++k) u[k] = (grp_lane<G>() == 0 && k == 0) ? 1u : 0u;
-    mont_mul_reg<S, G>(A, A, u, abuf, n, n0inv);
+    mont_mul_reg<S, G, B>(A, A, u, abuf, n, n0inv);
 }
 
 // ---- out[i] = base[i]^exp[i] mod mod[i] --------------------------------
-template <int S, int G>
+//
+// S limbs of radix 2^B hold the caller's `limbs` 32-bit words (B*S >= 32*limbs).
+template <int S, int G, int B>
 __global__ __launch_bounds__(64) void k_modexp(const uint32_t *__restrict__ base,
                                                const uint32_t *__restrict__ exp,
                                                const uint32_t *__restrict__ mod,
                                                uint32_t *out, unsigned long long count, int limbs, int w,
                                                unsigned long long *errs)
 {
+    using Ar = Arith<S, G, B>;
+    using Ly = Layout<S, G>;
     constexpr int L = S / G, NG = 64 / G;
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
     const int g = grp_index<G>(), r = grp_lane<G>();
@@ -225,35 +314,37 @@ __global__ __launch_bounds__(64) void k_modexp(const uint32_t *__restrict__ base
     const size_t off = live ? (size_t)msg * (size_t)limbs : 0;
 
     uint32_t n[L], x[L];
-    load_limbs<S, G>(n, mod + off, limbs, live);
-    load_limbs<S, G>(x, base + off, limbs, live);
-    const uint32_t n0 = grp_bcast<G>(n[0], 0);
-    const uint32_t bl = grp_bitlen<S, G>(n);
+    Ar::load(n, mod + off, limbs, 0, live);
+    Ar::load(x, base + off, limbs, 0, live);
+    const uint32_t n0 = grp_bcast0<G>(n[0]);
+    const uint32_t bl = Ar::bitlen(n);
     const bool valid = live && (n0 & 1u) && bl > 1;
-    const uint32_t n0inv = neg_inv32(n0 | 1u);
+    const uint32_t n0inv = Ar::n0inv(n0 | 1u);
 
     uint32_t one[L], r2[L], xt[L], A[L];
-    mont_setup<S, G>(one, r2, n, n0inv, valid, lds);
-    mont_mul_reg<S, G>(xt, x, r2, lds, n, n0inv);
-    group_modexp<S, G>(A, xt, exp + off, limbs, valid, n, n0inv, one, lds, w);
-    from_mont<S, G>(A, lds, n, n0inv);
+    mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds, lds + Ly::WORDS);
+    mont_mul_reg<S, G, B>(xt, x, r2, lds, n, n0inv);
+    group_modexp<S, G, B>(A, xt, exp + off, limbs, valid, n, n0inv, one, lds, w);
+    from_mont<S, G, B>(A, lds, n, n0inv);
 
-    store_limbs<S, G>(out + off, A, limbs, live, valid);
+    store_words<S, G, B>(out + off, A, limbs, live, valid, lds);
     if (live && r == 0 && !valid && bl != 1) atomicAdd(errs, 1ull);
 }
 
 // ---- CRT decryption ------------------------------------------------------
 //
 // Groups come in pairs: even group = the half modulo p, odd group = modulo q
-// of the same message; H is the (padded) width of p and q, hl their actual
-// limb count, and the message c and result have 2*hl limbs.
-template <int H, int G>
+// of the same message.  p, q, dp, dq, qinv have hl 32-bit words, c and the
+// result 2*hl; H limbs of radix 2^B hold a half (B*H >= 32*hl).
+template <int H, int G, int B>
 __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, const uint32_t *__restrict__ p,
                                             const uint32_t *__restrict__ q, const uint32_t *__restrict__ dp,
                                             const uint32_t *__restrict__ dq, const uint32_t *__restrict__ qinv,
                                             uint32_t *out, unsigned long long count, int hl, int w,
                                             unsigned long long *errs)
 {
+    using Ar = Arith<H, G, B>;
+    using Ly = Layout<H, G>;
     constexpr int L = H / G, NG = 64 / G;
     static_assert(NG >= 2, "a wave holds at least one pair of groups");
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
@@ -263,18 +354,19 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
     const bool live = msg < count;
     const size_t hoff = live ? (size_t)msg * (size_t)hl : 0;
     const size_t foff = 2 * hoff;
+    const int full = 2 * hl;
 
     uint32_t n[L], clo[L], chi[L], other[L];
-    load_limbs<H, G>(n, (half ? q : p) + hoff, hl, live);
-    load_limbs<H, G>(other, (half ? p : q) + hoff, hl, live);   // p-groups need q
-    load_limbs<H, G>(clo, c + foff, hl, live);
-    load_limbs<H, G>(chi, c + foff + hl, hl, live);
-    const uint32_t n0 = grp_bcast<G>(n[0], 0);
-    const uint32_t bl = grp_bitlen<H, G>(n);
+    Ar::load(n, (half ? q : p) + hoff, hl, 0, live);
+    Ar::load(other, (half ? p : q) + hoff, hl, 0, live);     // p-groups need q
+    Ar::load(clo, c + foff, full, 0, live);                   // c mod R
+    Ar::load(chi, c + foff, full, B * H, live);               // c div R
+    const uint32_t n0 = grp_bcast0<G>(n[0]);
+    const uint32_t bl = Ar::bitlen(n);
     bool valid = live && (n0 & 1u) && bl > 1;
     {   // p > q, evaluated by every group and used by the p-groups
         uint32_t d[L];
-        const uint32_t lt = grp_sub<H, G>(d, n, other);
+        const uint32_t lt = Ar::sub(d, n, other);
         bool nz = false;
 #pragma unroll
         for (int k = 0; k < L; ++k) nz = nz || d[k] != 0u;
@@ -287,26 +379,24 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
         const bool bad = (__ballot(!valid) & pmask) != 0;
         valid = valid && !bad;
     }
-    const uint32_t n0inv = neg_inv32(n0 | 1u);
+    const uint32_t n0inv = Ar::n0inv(n0 | 1u);
 
-    uint32_t one[L], r2[L], k3[L], y[L];
-    mont_setup<H, G>(one, r2, n, n0inv, valid, lds);
-    // y = 2^(32 hl) * R mod n: r2 when hl == H, else one doubled 32*hl times
-#pragma unroll
-    for (int k = 0; k < L; ++k) y[k] = (hl == H) ? r2[k] : one[k];
-    if (hl != H)
-        for (int t = 0; t < 32 * hl; ++t) grp_dbl_mod<H, G>(y, n);
-    mont_mul_reg<H, G>(k3, y, r2, lds, n, n0inv);          // 2^(32 hl) * R^2 mod n
+    uint32_t one[L], r2[L], r3[L];
+    mont_setup<H, G, B>(one, r2, n, n0inv, valid, lds, lds + Ly::WORDS);
+    mont_mul_reg<H, G, B>(r3, r2, r2, lds, n, n0inv);        // R^3 mod n
 
-    // xt = c * R mod n = c_lo * R + c_hi * 2^(32 hl) * R
+    // xt = c * R mod n = c_lo * R + c_hi * R * R  (c = c_lo + c_hi * R)
     uint32_t xt[L], t2[L];
-    mont_mul_reg<H, G>(xt, clo, r2, lds, n, n0inv);
-    mont_mul_reg<H, G>(t2, chi, k3, lds, n, n0inv);
-    grp_add_mod<H, G>(xt, t2, n);
+    mont_mul_reg<H, G, B>(xt, clo, r2, lds, n, n0inv);
+    mont_mul_reg<H, G, B>(t2, chi, r3, lds, n, n0inv);
+    {
+        const uint32_t ovf = Ar::add(xt, t2);
+        Ar::cond_sub(xt, ovf, n);
+    }
 
     uint32_t A[L];
-    group_modexp<H, G>(A, xt, (half ? dq : dp) + hoff, hl, valid, n, n0inv, one, lds, w);
-    from_mont<H, G>(A, lds, n, n0inv);
+    group_modexp<H, G, B>(A, xt, (half ? dq : dp) + hoff, hl, valid, n, n0inv, one, lds, w);
+    from_mont<H, G, B>(A, lds, n, n0inv);
 
     // Garner: h = qinv * (m_p - m_q) mod p, m = m_q + h * q  (on the p-group)
     uint32_t mq[L], qv[L], hh[L];
@@ -314,29 +404,41 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
     lds_put<H, G>(lds, A);
     lds_sync();
     lds_get<H, G>(mq, lds, g ^ 1);
-    grp_sub_mod<H, G>(A, mq, n);                            // delta = m_p - m_q mod p
-    load_limbs<H, G>(qv, qinv + hoff, hl, live && !half);
-    mont_mul_reg<H, G>(qv, qv, r2, lds, n, n0inv);          // qinv * R mod p
-    mont_mul_reg<H, G>(hh, A, qv, lds, n, n0inv);           // delta * qinv mod p
+    {   // delta = m_p - m_q mod p
+        uint32_t d[L];
+        const uint32_t neg = Ar::sub(d, A, mq);
+        uint32_t e[L];
+#pragma unroll
+        for (int k = 0; k < L; ++k) e[k] = d[k];
+        Ar::add(e, n);
+#pragma unroll
+        for (int k = 0; k < L; ++k) A[k] = neg ? e[k] : d[k];
+    }
+    Ar::load(qv, qinv + hoff, hl, 0, live && !half);
+    mont_mul_reg<H, G, B>(qv, qv, r2, lds, n, n0inv);         // qinv * R mod p
+    mont_mul_reg<H, G, B>(hh, A, qv, lds, n, n0inv);          // delta * qinv mod p
     lds_sync();
     lds_put<H, G>(lds, hh);
     lds_sync();
-    const int full = 2 * hl;
-    uint32_t *o = out + foff;
-    const bool write = live && !half;
+    // m = m_q + h * q: 2H limbs, staged in LDS after the operand buffer
+    uint32_t *stage = lds + Ly::WORDS + g * (2 * H);
     auto sink = [&](int i, uint32_t v) {
-        if (write && r == 0 && i < full) o[i] = valid ? v : 0u;
+        if (r == 0) stage[i] = v;
     };
     uint32_t high[L];
-    mul_wide<H, G>(high, mq, other, lds, sink);
-    if (write) {
+    Ar::mul_wide(high, mq, other, lds, sink);
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            const int li = H + r * L + k;
-            if (li < full) o[li] = valid ? high[k] : 0u;
+    for (int k = 0; k < L; ++k) stage[H + r * L + k] = high[k];
+    lds_sync();
+    if (live && !half) {
+        uint32_t *o = out + foff;
+        if constexpr (B == 32) {
+            for (int wd = r; wd < full; wd += G) o[wd] = valid ? stage[wd] : 0u;
+        } else {
+            for (int wd = r; wd < full; wd += G) o[wd] = valid ? rword<B>(stage, 2 * H, wd) : 0u;
         }
     }
-    if (write && r == 0 && !valid) atomicAdd(errs, 1ull);
+    if (live && !half && r == 0 && !valid) atomicAdd(errs, 1ull);
 }
 
 }  // namespace rsagpu

@@ -1,0 +1,303 @@
+// Lane-group multi-precision arithmetic in radix 2^B, B < 32 (reduced radix).
+//
+// Same lane-group layout as group_bn.hpp (G lanes per integer, L = S / G limbs
+// per lane), but every limb holds B < 32 bits in a 32-bit word.  A product of
+// two limbs is below 2^(2B), so a 64-bit accumulator absorbs 2^(64 - 2B)
+// products without overflow: the Montgomery loop is one v_mad_u64_u32 per
+// product with no carry detection at all.  For B = 29 that is 64 products; the
+// CIOS loop adds two products per limb position per step, so the positions
+// are partially normalised (each keeps its low B bits and hands the rest to
+// the next position) every 31 steps or fewer.
+//
+// Integers enter and leave in the caller's 32-bit-limb format; conversion
+// happens at load time (each lane reads the 32-bit words that hold its limbs)
+// and at store time (through LDS, since an output word can straddle lanes).
+#pragma once
+
+#include "group_bn.hpp"
+
+namespace rsagpu {
+
+template <int B>
+struct Radix {
+    static_assert(B >= 24 && B <= 30, "reduced radix");
+    static constexpr uint32_t MASK = (1u << B) - 1u;
+};
+
+// ---- conversion ------------------------------------------------------------
+
+// Limbs [r*L, r*L + L) of the B-bit-limb form of (number at p >> bitoff),
+// where the number has nwords 32-bit words (zero beyond; zero when !live).
+template <int S, int G, int B>
+__device__ __forceinline__ void rload(uint32_t (&x)[S / G], const uint32_t *p, int nwords, int bitoff, bool live)
+{
+    constexpr int L = S / G;
+    const int r = grp_lane<G>();
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const int pos = bitoff + B * (r * L + k);
+        const int w = pos >> 5, sh = pos & 31;
+        const uint32_t lo = (live && w < nwords) ? p[w] : 0u;
+        const uint32_t hi = (live && w + 1 < nwords) ? p[w + 1] : 0u;
+        const uint64_t v = (((uint64_t)hi << 32) | lo) >> sh;
+        x[k] = (uint32_t)v & Radix<B>::MASK;
+    }
+}
+
+// Word k (32 bits) of an integer held as `nlimbs` B-bit limbs at q[0 ..].
+template <int B>
+__device__ __forceinline__ uint32_t rword(const uint32_t *q, int nlimbs, int k)
+{
+    const int pos = 32 * k;
+    const int j = pos / B, sh = pos % B;
+    const uint64_t l0 = j < nlimbs ? q[j] : 0u;
+    const uint64_t l1 = j + 1 < nlimbs ? q[j + 1] : 0u;
+    const uint64_t l2 = j + 2 < nlimbs ? q[j + 2] : 0u;
+    const uint64_t v = (l0 | (l1 << B)) >> sh;
+    return (uint32_t)(v | (l2 << (2 * B - sh)));
+}
+
+// ---- group-wide add / subtract / compare ---------------------------------
+
+template <int S, int G, int B>
+__device__ __forceinline__ uint32_t rgrp_add(uint32_t (&x)[S / G], const uint32_t (&y)[S / G])
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+    uint32_t c = 0;
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t t = x[j] + y[j] + c;
+        x[j] = t & M;
+        c = t >> B;
+        all = all && x[j] == M;
+    }
+    uint32_t k = grp_carry_in<G>(c != 0, all);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t t = x[j] + k;
+        x[j] = t & M;
+        k = t >> B;
+    }
+    return grp_top_flag<G>((c | k) != 0) ? 1u : 0u;
+}
+
+template <int S, int G, int B>
+__device__ __forceinline__ uint32_t rgrp_sub(uint32_t (&d)[S / G], const uint32_t (&x)[S / G],
+                                             const uint32_t (&y)[S / G])
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+    uint32_t b = 0, any = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t t = x[j] - y[j] - b;
+        d[j] = t & M;
+        b = t >> 31;
+        any |= d[j];
+    }
+    uint32_t k = grp_carry_in<G>(b != 0, any == 0u);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t t = d[j] - k;
+        d[j] = t & M;
+        k = t >> 31;
+    }
+    return grp_top_flag<G>((b | k) != 0) ? 1u : 0u;
+}
+
+template <int S, int G, int B>
+__device__ __forceinline__ void rgrp_cond_sub(uint32_t (&x)[S / G], uint32_t top, const uint32_t (&n)[S / G])
+{
+    constexpr int L = S / G;
+    uint32_t d[L];
+    const uint32_t borrow = rgrp_sub<S, G, B>(d, x, n);
+    const bool take = grp_top_flag<G>(top != 0) || !borrow;
+#pragma unroll
+    for (int j = 0; j < L; ++j) x[j] = take ? d[j] : x[j];
+}
+
+template <int S, int G, int B>
+__device__ __forceinline__ void rgrp_dbl_mod(uint32_t (&x)[S / G], const uint32_t (&n)[S / G])
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+    const uint32_t out = x[L - 1] >> (B - 1);
+    const uint32_t in = grp_from_below<G>(out);
+#pragma unroll
+    for (int j = L - 1; j > 0; --j) x[j] = ((x[j] << 1) & M) | (x[j - 1] >> (B - 1));
+    x[0] = ((x[0] << 1) & M) | in;
+    rgrp_cond_sub<S, G, B>(x, out, n);
+}
+
+template <int S, int G, int B>
+__device__ __forceinline__ uint32_t rgrp_bitlen(const uint32_t (&x)[S / G])
+{
+    constexpr int L = S / G;
+    uint32_t bl = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+        if (x[j]) bl = (uint32_t)(B * (grp_lane<G>() * L + j) + 32 - __clz(x[j]));
+    return grp_max<G>(bl);
+}
+
+// ---- accumulator normalisation -----------------------------------------
+
+// Partial: every position keeps its low B bits and passes the rest to the
+// next position; the top position of a lane passes it to the lane above (the
+// group's top lane keeps it, it is the part beyond S limbs).  The value is
+// unchanged and every position drops below 2^B + 2^(64-B).
+template <int S, int G, int B>
+__device__ __forceinline__ void racc_squeeze(uint64_t (&acc)[S / G])
+{
+    constexpr int L = S / G;
+    const bool top = grp_lane<G>() == G - 1;
+    uint64_t c[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) c[j] = acc[j] >> B;
+    if (top) c[L - 1] = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[j] = (j == L - 1 && top) ? acc[j] : (acc[j] & Radix<B>::MASK);
+#pragma unroll
+    for (int j = L - 1; j > 0; --j) acc[j] += c[j - 1];
+    const uint32_t rlo = grp_from_below<G>((uint32_t)c[L - 1]);
+    const uint32_t rhi = grp_from_below<G>((uint32_t)(c[L - 1] >> 32));
+    acc[0] += ((uint64_t)rhi << 32) | rlo;
+}
+
+// Full: canonical B-bit limbs in w, returns the group's overflow beyond S
+// limbs (meaningful in the top lane).
+template <int S, int G, int B>
+__device__ __forceinline__ uint32_t racc_normalise(uint32_t (&w)[S / G], const uint64_t (&acc)[S / G])
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+    static_assert(L >= 2, "at least two limbs per lane");
+    uint64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint64_t t = acc[j] + c;
+        w[j] = (uint32_t)t & M;
+        c = t >> B;
+    }
+    const bool top = grp_lane<G>() == G - 1;
+    const uint32_t rlo = grp_from_below<G>((uint32_t)c), rhi = grp_from_below<G>((uint32_t)(c >> 32));
+    const uint64_t own = top ? c : 0;
+    uint64_t t = (uint64_t)w[0] + (((uint64_t)rhi << 32) | rlo);
+    w[0] = (uint32_t)t & M;
+    uint32_t k = (uint32_t)(t >> B);
+#pragma unroll
+    for (int j = 1; j < L; ++j) {
+        const uint32_t u = w[j] + k;
+        w[j] = u & M;
+        k = u >> B;
+    }
+    bool all = true;
+#pragma unroll
+    for (int j = 0; j < L; ++j) all = all && w[j] == M;
+    uint32_t k2 = grp_carry_in<G>(k != 0, all);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t u = w[j] + k2;
+        w[j] = u & M;
+        k2 = u >> B;
+    }
+    return top ? ((own != 0) | k | k2) : 0u;
+}
+
+// ---- Montgomery product, radix 2^B -----------------------------------------
+//
+// r = a * b * 2^(-B*S) mod n for a < 2^(BS) in registers and b < n in the
+// group's slot of LDS buffer bbuf (or a < n, b < 2^(BS)); n0inv = -n^-1 mod 2^B.
+template <int S, int G, int B>
+__device__ __forceinline__ void rmont_mul(uint32_t (&r)[S / G], const uint32_t (&a)[S / G], const uint32_t *bbuf,
+                                          const uint32_t (&n)[S / G], uint32_t n0inv)
+{
+    using Ly = Layout<S, G>;
+    constexpr int L = Ly::L, V = Ly::V;
+    constexpr uint32_t M = Radix<B>::MASK;
+    // steps between squeezes: two products per position per step
+    constexpr int KMAX = ((1 << (64 - 2 * B)) - 2) / 2;
+    constexpr int NB = KMAX / L;
+    static_assert(NB >= 1, "limbs per lane too large for the radix");
+    const int g = grp_index<G>();
+    uint64_t acc[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[j] = 0;
+
+    int blk = 0;
+    for (int i0 = 0; i0 < S; i0 += L, ++blk) {
+        if (blk == NB) {
+            racc_squeeze<S, G, B>(acc);
+            blk = 0;
+        }
+        uint32_t bv[L];
+#pragma unroll
+        for (int k = 0; k < L; k += V) {
+            typename VecT<V>::T v = *reinterpret_cast<const typename VecT<V>::T *>(bbuf + Ly::at(i0 + k, g));
+            const uint32_t *pv = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+            for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
+        }
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+#pragma unroll
+            for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * bv[k];
+            const int p0 = k % L, p1 = (k + 1) % L;
+            const uint32_t m = grp_bcast0<G>(((uint32_t)acc[p0] * n0inv) & M);
+#pragma unroll
+            for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)m * n[j];
+            acc[p1] += acc[p0] >> B;
+            // the group's lane 0 holds zero in its low B bits here
+            acc[p0] = grp_rot_down<G>((uint32_t)acc[p0] & M);
+        }
+    }
+    const uint32_t top = racc_normalise<S, G, B>(r, acc);
+    rgrp_cond_sub<S, G, B>(r, top, n);
+}
+
+// (low, high) = init + a * b (no reduction), b in LDS; lane 0 of the group
+// passes low limb i to sink(i, limb); high gets the upper S limbs.
+template <int S, int G, int B, typename Sink>
+__device__ __forceinline__ void rmul_wide(uint32_t (&high)[S / G], const uint32_t (&init)[S / G],
+                                          const uint32_t (&a)[S / G], const uint32_t *bbuf, Sink sink)
+{
+    using Ly = Layout<S, G>;
+    constexpr int L = Ly::L, V = Ly::V;
+    constexpr uint32_t M = Radix<B>::MASK;
+    constexpr int KMAX = (1 << (64 - 2 * B)) - 2;
+    constexpr int NB = KMAX / L;
+    const int g = grp_index<G>();
+    uint64_t acc[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[j] = init[j];
+
+    int blk = 0;
+    for (int i0 = 0; i0 < S; i0 += L, ++blk) {
+        if (blk == NB) {
+            racc_squeeze<S, G, B>(acc);
+            blk = 0;
+        }
+        uint32_t bv[L];
+#pragma unroll
+        for (int k = 0; k < L; k += V) {
+            typename VecT<V>::T v = *reinterpret_cast<const typename VecT<V>::T *>(bbuf + Ly::at(i0 + k, g));
+            const uint32_t *pv = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+            for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
+        }
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+#pragma unroll
+            for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * bv[k];
+            const int p0 = k % L, p1 = (k + 1) % L;
+            sink(i0 + k, (uint32_t)acc[p0] & M);
+            acc[p1] += acc[p0] >> B;
+            acc[p0] = grp_from_above<G>((uint32_t)acc[p0] & M);
+        }
+    }
+    racc_normalise<S, G, B>(high, acc);
+}
+
+}  // namespace rsagpu

@@ -12,6 +12,7 @@
 namespace rsagpu {
 
 struct Instance {
+    int B;
     int S;
     int G;
     modexp_launcher modexp;
@@ -19,52 +20,67 @@ struct Instance {
 };
 
 static const Instance kInstances[] = {
-#define X(S_, G_) {S_, G_, &launch_modexp<S_, G_>, &launch_crt<S_, G_>},
+#define X(B_, S_, G_) {B_, S_, G_, &launch_modexp<S_, G_, B_>, &launch_crt<S_, G_, B_>},
 #include "instances.def"
 #undef X
 };
 
-static const int kWidths[] = {2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
-static const int kNumWidths = sizeof(kWidths) / sizeof(kWidths[0]);
+// Width classes in 32-bit limbs; a call runs at the smallest class that holds
+// its `limbs`.  kS29 is the limb count of the same class in radix 2^29
+// (29 * kS29 >= 32 * class), 0 where no radix-2^29 instance exists.
+static const int kClasses[] = {2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
+static const int kS29[] = {0, 0, 0, 0, 18, 28, 36, 56, 72, 112, 144};
+static const int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
-// Default plan per padded width: lanes per exponentiation G (limbs per lane
-// L = S / G) and window bits w.  kind 0 = plain exponentiation, kind 1 = CRT
-// half.  L stays near 8 so the per-step cross-lane work is amortised over 2L
-// products, and the window is the largest whose 2^w operand buffers per wave
-// (2^w * 256 * L bytes of LDS) still let 8 waves share a CU's 160 KiB: with
-// fewer resident waves the dependency chain of each Montgomery step (product,
-// m, broadcast, products) is no longer hidden, which costs far more than the
-// extra multiplications of a narrower window.
+// Default plan per class: limb radix 2^B, lanes per exponentiation G (limbs
+// per lane L = S / G) and window bits w.  From 512-bit operands up the
+// reduced radix 2^29 wins (one v_mad_u64_u32 per product, no carry handling,
+// despite ~21% more limb products); below, radix 2^32.  kind 0 = plain exponentiation,
+// kind 1 = CRT half.  L stays near 8 so the per-step cross-lane work is
+// amortised over 2L products, and the window is the largest whose 2^w
+// operand buffers per wave (2^w * 256 * L bytes of LDS) still let 8 waves
+// share a CU's 160 KiB: with fewer resident waves the dependency chain of
+// each Montgomery step (product, m, broadcast, products) is no longer hidden,
+// which costs far more than the extra multiplications of a narrower window.
 struct Plan {
+    int B;
     int G;
     int w;
 };
-static const Plan kDefault[2][kNumWidths] = {
-    {{1, 4}, {1, 4}, {1, 3}, {2, 3}, {2, 3}, {4, 3}, {4, 3}, {4, 3}, {8, 3}, {8, 3}, {16, 3}},
-    {{1, 4}, {1, 4}, {1, 3}, {2, 3}, {2, 3}, {4, 3}, {4, 3}, {4, 3}, {8, 3}, {8, 3}, {16, 3}},
+static const Plan kDefault[2][kNumClasses] = {
+    // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 4, 2}, {29, 8, 3},
+     {29, 8, 2}, {29, 16, 3}, {29, 16, 2}},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 4, 3}, {29, 8, 3},
+     {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
 };
 
-// Current plans (packed G << 8 | w); overridable with rsa_set_plan.
-static std::atomic<int> g_plan[2][kNumWidths];
+static int pack(const Plan &p) { return p.B << 16 | p.G << 8 | p.w; }
+static Plan unpack(int v) { return Plan{v >> 16, (v >> 8) & 0xFF, v & 0xFF}; }
+
+// Current plans; overridable with rsa_set_plan.
+static std::atomic<int> g_plan[2][kNumClasses];
 static std::once_flag g_plan_once;
 
 static void init_plans()
 {
     for (int k = 0; k < 2; ++k)
-        for (int i = 0; i < kNumWidths; ++i) g_plan[k][i].store(kDefault[k][i].G << 8 | kDefault[k][i].w);
+        for (int i = 0; i < kNumClasses; ++i) g_plan[k][i].store(pack(kDefault[k][i]));
 }
 
-static int width_index(int limbs)
+static int class_index(int limbs)
 {
-    for (int i = 0; i < kNumWidths; ++i)
-        if (kWidths[i] >= limbs) return i;
+    for (int i = 0; i < kNumClasses; ++i)
+        if (kClasses[i] >= limbs) return i;
     return -1;
 }
 
-static const Instance *find_instance(int S, int G)
+static const Instance *find_instance(int i, int B, int G)
 {
+    const int S = B == 32 ? kClasses[i] : (B == 29 ? kS29[i] : 0);
+    if (S == 0) return nullptr;
     for (const Instance &in : kInstances)
-        if (in.S == S && in.G == G) return &in;
+        if (in.B == B && in.S == S && in.G == G) return &in;
     return nullptr;
 }
 
@@ -76,11 +92,11 @@ struct Resolved {
 static bool resolve(int limbs, int kind, Resolved *r)
 {
     std::call_once(g_plan_once, init_plans);
-    const int i = width_index(limbs);
+    const int i = class_index(limbs);
     if (i < 0) return false;
-    const int packed = g_plan[kind][i].load();
-    r->inst = find_instance(kWidths[i], packed >> 8);
-    r->w = packed & 0xFF;
+    const Plan p = unpack(g_plan[kind][i].load());
+    r->inst = find_instance(i, p.B, p.G);
+    r->w = p.w;
     return r->inst != nullptr;
 }
 
@@ -164,6 +180,7 @@ extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)
     if (limbs < 1 || limbs > RSA_MAX_LIMBS) return RSA_ELIMBS;
     Resolved r;
     if (!resolve(limbs, kind, &r)) return RSA_ELIMBS;
+    plan->radix_bits = r.inst->B;
     plan->padded_limbs = r.inst->S;
     plan->lanes_per_op = r.inst->G;
     plan->limbs_per_lane = r.inst->S / r.inst->G;
@@ -172,21 +189,22 @@ extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)
     return RSA_OK;
 }
 
-extern "C" int rsa_set_plan(int limbs, int kind, int lanes_per_op, int window_bits)
+extern "C" int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int window_bits)
 {
     if (kind != 0 && kind != 1) return RSA_EINVAL;
     if (limbs < 1 || limbs > RSA_MAX_LIMBS) return RSA_ELIMBS;
     std::call_once(g_plan_once, init_plans);
-    const int i = width_index(limbs);
+    const int i = class_index(limbs);
     if (i < 0) return RSA_ELIMBS;
-    if (lanes_per_op == 0 && window_bits == 0) {           // back to the default
-        g_plan[kind][i].store(kDefault[kind][i].G << 8 | kDefault[kind][i].w);
+    if (radix_bits == 0 && lanes_per_op == 0 && window_bits == 0) {   // back to the default
+        g_plan[kind][i].store(pack(kDefault[kind][i]));
         return RSA_OK;
     }
-    if (!find_instance(kWidths[i], lanes_per_op)) return RSA_EINVAL;
-    if (window_bits < 1 || window_bits > 7) return RSA_EINVAL;
-    if (lds_bytes_for(kWidths[i], lanes_per_op, window_bits) > 64 * 1024) return RSA_EINVAL;
-    g_plan[kind][i].store(lanes_per_op << 8 | window_bits);
+    const Instance *in = find_instance(i, radix_bits, lanes_per_op);
+    if (!in) return RSA_EINVAL;
+    if (window_bits < 2 || window_bits > 7) return RSA_EINVAL;
+    if (lds_bytes_for(in->S, in->G, window_bits) > 64 * 1024) return RSA_EINVAL;
+    g_plan[kind][i].store(pack(Plan{radix_bits, lanes_per_op, window_bits}));
     return RSA_OK;
 }
 

@@ -37,14 +37,14 @@ _lib.rsa_version.restype = ctypes.c_int
 
 
 class _Plan(ctypes.Structure):
-    _fields_ = [("padded_limbs", ctypes.c_int), ("lanes_per_op", ctypes.c_int),
+    _fields_ = [("radix_bits", ctypes.c_int), ("padded_limbs", ctypes.c_int), ("lanes_per_op", ctypes.c_int),
                 ("limbs_per_lane", ctypes.c_int), ("window_bits", ctypes.c_int),
                 ("lds_bytes", ctypes.c_int)]
 
 
 _lib.rsa_get_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Plan)]
 _lib.rsa_get_plan.restype = ctypes.c_int
-_lib.rsa_set_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+_lib.rsa_set_plan.argtypes = [ctypes.c_int] * 5
 _lib.rsa_set_plan.restype = ctypes.c_int
 _lib.rsa_init.argtypes = []
 _lib.rsa_init.restype = ctypes.c_int
@@ -67,6 +67,7 @@ def _check(status: int, what: str) -> None:
 
 @dataclass
 class Plan:
+    radix_bits: int
     padded_limbs: int
     lanes_per_op: int
     limbs_per_lane: int
@@ -77,12 +78,12 @@ class Plan:
 def get_plan(limbs: int, kind: int = 0) -> Plan:
     p = _Plan()
     _check(_lib.rsa_get_plan(limbs, kind, ctypes.byref(p)), "rsa_get_plan")
-    return Plan(p.padded_limbs, p.lanes_per_op, p.limbs_per_lane, p.window_bits, p.lds_bytes)
+    return Plan(p.radix_bits, p.padded_limbs, p.lanes_per_op, p.limbs_per_lane, p.window_bits, p.lds_bytes)
 
 
-def set_plan(limbs: int, kind: int, lanes_per_op: int, window_bits: int) -> None:
-    """Override the plan of a limb width (0, 0 restores the default)."""
-    _check(_lib.rsa_set_plan(limbs, kind, lanes_per_op, window_bits), "rsa_set_plan")
+def set_plan(limbs: int, kind: int, radix_bits: int, lanes_per_op: int, window_bits: int) -> None:
+    """Override the plan of a limb width (all zero restores the default)."""
+    _check(_lib.rsa_set_plan(limbs, kind, radix_bits, lanes_per_op, window_bits), "rsa_set_plan")
 
 
 def init() -> None:

@@ -62,9 +62,22 @@ def test_plans_are_consistent():
     for limbs in range(1, 129):
         for kind in (0, 1):
             p = rsagpu.get_plan(limbs, kind)
-            assert p.padded_limbs >= limbs
+            assert p.radix_bits * p.padded_limbs >= 32 * limbs
             assert p.lanes_per_op * p.limbs_per_lane == p.padded_limbs
             assert p.limbs_per_lane >= 2 and 64 % p.lanes_per_op == 0
             assert p.lds_bytes <= 64 * 1024
     with pytest.raises(Exception):
         rsagpu.get_plan(0, 0)
+    # overrides: a compiled instance is accepted, anything else refused
+    default = rsagpu.get_plan(32, 1)
+    rsagpu.set_plan(32, 1, 32, 8, 2)
+    p = rsagpu.get_plan(32, 1)
+    assert (p.radix_bits, p.padded_limbs, p.lanes_per_op, p.window_bits) == (32, 32, 8, 2)
+    rsagpu.set_plan(32, 1, 29, 2, 3)
+    p = rsagpu.get_plan(32, 1)
+    assert (p.radix_bits, p.padded_limbs, p.lanes_per_op, p.window_bits) == (29, 36, 2, 3)
+    for bad in ((32, 1, 29, 3, 3), (32, 1, 31, 4, 3), (32, 1, 32, 4, 1), (32, 1, 32, 2, 6), (8, 0, 29, 2, 3)):
+        with pytest.raises(Exception):
+            rsagpu.set_plan(*bad)
+    rsagpu.set_plan(32, 1, 0, 0, 0)
+    assert rsagpu.get_plan(32, 1) == default

@@ -1,0 +1,102 @@
+"""Every compiled kernel instance (limb radix, width, lanes per exponentiation)
+against the CPU oracle, bit-exact, for both plain exponentiation and CRT
+decryption.  Each instance is selected with rsa_set_plan and restored after."""
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from paper_1407_1465_amd import workloads as W
+from gpu_util import dev, host, oracle_modexp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1407_1465_amd import rsagpu  # noqa: E402
+
+DEF = os.path.join(ROOT, "paper_1407_1465_amd", "csrc", "instances.def")
+INSTANCES = [tuple(map(int, m)) for m in re.findall(r"X\((\d+), (\d+), (\d+)\)", open(DEF).read())]
+# radix-2^29 limb count -> the 32-bit width class it serves
+CLASS_OF_S29 = {18: 16, 28: 24, 36: 32, 56: 48, 72: 64, 112: 96, 144: 128}
+
+
+def width_class(B, S):
+    return S if B == 32 else CLASS_OF_S29[S]
+
+
+def window_for(B, S, G):
+    for w in (3, 2):
+        if (1 << w) * S * (64 // G) * 4 <= 64 * 1024:
+            return w
+    raise AssertionError("no window fits")
+
+
+@pytest.fixture
+def plan_guard():
+    touched = []
+    yield touched
+    for limbs, kind in touched:
+        rsagpu.set_plan(limbs, kind, 0, 0, 0)
+
+
+@pytest.mark.parametrize("B,S,G", INSTANCES)
+def test_instance_modexp(B, S, G, plan_guard):
+    cls = width_class(B, S)
+    rsagpu.set_plan(cls, 0, B, G, window_for(B, S, G))
+    plan_guard.append((cls, 0))
+    p = rsagpu.get_plan(cls, 0)
+    assert (p.radix_bits, p.padded_limbs, p.lanes_per_op) == (B, S, G)
+    rng = random.Random(B * 1000 + S * 10 + G)
+    for limbs in sorted({cls, max(1, cls - 1)}):
+        ng = 64 // G
+        count = ng + 3 if cls >= 64 else 2 * ng + 3
+        bits = 32 * limbs
+        mods = [rng.getrandbits(bits) | (1 << (bits - 1)) | 1 for _ in range(count)]
+        mods[1] = (1 << bits) - 1
+        mods[2] = rng.getrandbits(bits // 2) | 1 | (1 << (bits // 2 - 1))   # short modulus
+        bases = [rng.getrandbits(bits) for _ in range(count)]
+        exps = [rng.getrandbits(rng.choice([bits, 17, bits // 3 + 1])) for _ in range(count)]
+        exps[0] = 0
+        exps[3] = 1
+        Bv, Ev, Mv = (W.ints_to_limbs(v, limbs) for v in (bases, exps, mods))
+        out = host(rsagpu.modexp(dev(Bv), dev(Ev), dev(Mv)))
+        want = oracle_modexp(Bv, Ev, Mv)
+        bad = np.nonzero((out != want).any(axis=1))[0]
+        assert bad.size == 0, "B=%d S=%d G=%d limbs=%d: %d bad, first %d" % (B, S, G, limbs, bad.size, bad[0])
+    assert rsagpu.device_errors() == 0
+
+
+@pytest.mark.parametrize("B,S,G", [i for i in INSTANCES if 64 // i[2] >= 2])
+def test_instance_crt(B, S, G, plan_guard):
+    cls = width_class(B, S)
+    rsagpu.set_plan(cls, 1, B, G, window_for(B, S, G))
+    plan_guard.append((cls, 1))
+    bits = 64 * cls
+    if bits > 4096:
+        pytest.skip("no keys above 4096 bits in the workloads")
+    keys = W.make_keys(bits, 4242 + bits, 2)
+    L = keys[0].limbs
+    h = L // 2
+    pairs = 32 // G
+    count = pairs + 3 if bits >= 2048 else 2 * pairs + 3
+    rng = random.Random(S * G + B)
+    key_of = np.arange(count) % 2
+    cs = [rng.randrange(keys[k].n) for k in key_of]
+    cs[0], cs[1] = 0, keys[1].n - 1
+    C = W.ints_to_limbs(cs, L)
+
+    def col(attr, width):
+        return np.ascontiguousarray(W.ints_to_limbs([getattr(k, attr) for k in keys], width)[key_of])
+
+    out = host(rsagpu.decrypt_crt(dev(C), dev(col("p", h)), dev(col("q", h)), dev(col("dp", h)),
+                                  dev(col("dq", h)), dev(col("qinv", h))))
+    want = oracle_modexp(C, col("d", L), col("n", L))
+    bad = np.nonzero((out != want).any(axis=1))[0]
+    assert bad.size == 0, "B=%d S=%d G=%d: %d bad" % (B, S, G, bad.size)
+    assert rsagpu.device_errors() == 0
