@@ -1,19 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark: batched RSA modular exponentiation on one MI355X.
 
-Default workload: 2048-bit RSA, 64 seeded keys, 16384 messages assigned
-round-robin, CRT decryption (two 1024-bit exponentiations with dp, dq and
-Garner recombination per message).  One step = one CRT-decryption pass over
-the whole batch, inputs resident in HBM.  The line printed is
+Default workload (the headline metric): 2048-bit RSA, 64 seeded keys, 16384
+messages assigned round-robin, CRT decryption (two 1024-bit exponentiations
+with dp, dq and Garner recombination per message).  One step = one CRT-
+decryption pass over the whole batch with inputs resident in HBM.  The JSON
+line carries
 
-  {"metric", "value" (decryptions/s), ..., "roofline": {...}, "cpu_baseline": {...}}
+  roofline:     the decryption kernel against the chip's 32x32-bit integer
+                multiply peak: algorithmic products per launch (Montgomery
+                products of the fixed-window method, 2h^2 + h each, plus the
+                recombination) over the kernel's mean launch time from HIP
+                events recorded on the stream it runs on;
+  cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) timed on a bounded
+                sample of the same messages on the host's cores.
 
-`roofline` rates the decryption kernel against the chip's 32-bit integer
-multiply peak: algorithmic 32x32-bit products per launch (Montgomery products
-of the fixed-window method, 2h^2 + h products each, plus the recombination)
-divided by the kernel's mean launch time from HIP events on its stream.
-`cpu_baseline` times the plain CPU oracle (C^d mod n, no CRT) on a bounded
-sample of the same messages on the host's cores.
+Other workloads (--workload): rsa64, rsa1024 (full-d decryption, no CRT),
+enc2048 (e = 65537 encryption of the default batch), mixed (32768 operations
+over 1024..4096-bit keys in one rsa_ops_batch call), serve (Poisson requests
+through the continuous-batching server: p50/p99 latency and throughput).
 """
 import argparse
 import json
@@ -24,9 +29,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# 256 CUs x 64 lanes x 2.4 GHz / 4: the 32x32->64-bit integer multiply
-# (v_mad_u64_u32) issues at a quarter of the full VALU rate.
-INT32_MUL_PEAK = 256 * 64 * 2.4e9 / 4
+# 256 CUs x 64 lanes x 2.4 GHz: one 32x32->64-bit product (v_mad_u64_u32) per
+# lane per clock at the full VALU rate.
+INT32_MUL_PEAK = 256 * 64 * 2.4e9
 METRIC = "2048-bit modexp/sec (CRT decrypt) on 1 GPU, %INT32-mul peak; p50/p99 latency"
 
 
@@ -37,17 +42,51 @@ def fixed_window_montmuls(ebits: int, w: int) -> int:
     return (nwin - 1) * (w + 1) + (1 << w)
 
 
-def crt_products(key, plan_w: int) -> int:
+def mont_products(s: int) -> int:
+    """32x32-bit products of one Montgomery product of s 32-bit limbs."""
+    return 2 * s * s + s
+
+
+def crt_products(key, w: int) -> int:
     h = key.limbs // 2
-    per_mont = 2 * h * h + h
-    mm = fixed_window_montmuls(key.dp.bit_length(), plan_w) + \
-        fixed_window_montmuls(key.dq.bit_length(), plan_w)
-    return mm * per_mont + (2 * h * h + h) + h * h
+    mm = fixed_window_montmuls(key.dp.bit_length(), w) + fixed_window_montmuls(key.dq.bit_length(), w)
+    return mm * mont_products(h) + mont_products(h) + h * h
 
 
-def modexp_products(key, ebits: int, plan_w: int) -> int:
-    s = key.limbs
-    return fixed_window_montmuls(ebits, plan_w) * (2 * s * s + s)
+def modexp_products(key, ebits: int, w: int) -> int:
+    return fixed_window_montmuls(ebits, w) * mont_products(key.limbs)
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, time.perf_counter() - wall0
+
+
+def roofline(products, ms, kernel):
+    achieved = products / (ms / 1e3)
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_MUL_PEAK / 1e12,
+            "unit": "T int32-mul/s", "frac": achieved / INT32_MUL_PEAK, "traffic": None,
+            "kernel": kernel, "products_per_launch": products}
+
+
+def cpu_baseline(oracle, base, exp, mod, gpu_out, ns, unit, what):
+    threads = min(16, os.cpu_count() or 1)
+    got, cwall, used = oracle.modexp_batch(base[:ns], exp[:ns], mod[:ns], nthreads=threads)
+    import numpy as np
+    if not np.array_equal(got, gpu_out[:ns]):
+        raise SystemExit("GPU output differs from the oracle on the CPU sample")
+    return {"value": ns / cwall, "unit": unit, "cores": used, "kind": "oracle",
+            "sample": "first %d messages of the same batch, %s, %.1f s wall" % (ns, what, cwall)}
 
 
 def main():
@@ -55,10 +94,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--count", type=int, default=16384)
-    ap.add_argument("--keys", type=int, default=64)
+    ap.add_argument("--workload", default="crt2048",
+                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve"])
+    ap.add_argument("--count", type=int, default=0, help="messages (0: the workload's size)")
     ap.add_argument("--cpu-sample", type=int, default=512,
-                    help="messages the CPU oracle decrypts for the baseline (0: skip)")
+                    help="messages the CPU oracle processes for the baseline (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -72,95 +113,161 @@ def main():
         hipbuild.build()
     from paper_1407_1465_amd import rsagpu
     from paper_1407_1465_amd import workloads as W
-
-    t0 = time.time()
-    wl = W.workload_c3(count=args.count, nkeys=args.keys)
-    L = wl.limbs
-    h = L // 2
-    print("# workload ready in %.1fs: %d keys, %d messages, %d-bit" %
-          (time.time() - t0, len(wl.keys), args.count, 32 * L), file=sys.stderr, flush=True)
-
-    def tab(attr, width):
-        return np.ascontiguousarray(
-            W.ints_to_limbs([getattr(k, attr) for k in wl.keys], width)[wl.key_of])
+    torch.cuda.set_device(0)
 
     def dev(a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
 
-    torch.cuda.set_device(0)
-    c = dev(wl.ctxt)
-    p, q, dp, dq, qi = (dev(tab(a, h)) for a in ("p", "q", "dp", "dq", "qinv"))
-    out = torch.empty_like(c)
-    plan = rsagpu.get_plan(h, 1)
+    def tab(wl, attr, width):
+        return np.ascontiguousarray(W.ints_to_limbs([getattr(k, attr) for k in wl.keys], width)[wl.key_of])
 
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = gpu_ms / args.steps
-    value = args.count / (ms_per_step / 1e3)
-    if rsagpu.device_errors() != 0:
-        raise SystemExit("device reported data errors")
-
-    # spot-check a few outputs against the round trip before reporting
-    e_full = dev(tab("e", L))
-    n_full = dev(tab("n", L))
-    idx = torch.arange(0, args.count, max(1, args.count // 64), device="cuda")
-    back = rsagpu.modexp(out[idx].contiguous(), e_full[idx].contiguous(), n_full[idx].contiguous())
-    if not torch.equal(back, c[idx]):
-        raise SystemExit("round-trip check failed")
-
-    products = sum(crt_products(wl.keys[k], plan.window_bits) for k in wl.key_of.tolist())
-    achieved = products / (ms_per_step / 1e3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_MUL_PEAK / 1e12,
-                "unit": "T int32-mul/s", "frac": achieved / INT32_MUL_PEAK, "traffic": None,
-                "kernel": "k_crt<32,%d>" % plan.lanes_per_op,
-                "products_per_launch": products}
-
+    line = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "data": "synthetic (seeded keys and messages)"}
     cpu = None
-    if args.cpu_sample > 0:
-        import oracle
-        ns = min(args.cpu_sample, args.count)
-        n_h = tab("n", L)[:ns]
-        d_h = tab("d", L)[:ns]
-        threads = min(16, os.cpu_count() or 1)
-        got, cwall, used = oracle.modexp_batch(wl.ctxt[:ns], d_h, n_h, nthreads=threads)
-        gpu_h = out[:ns].cpu().numpy().view(np.uint32)
-        if not np.array_equal(got, gpu_h):
-            raise SystemExit("GPU output differs from the oracle on the CPU sample")
-        cpu = {"value": ns / cwall, "unit": "decryptions/s", "cores": used, "kind": "oracle",
-               "sample": "first %d messages of the same batch, plain C^d mod n (no CRT), "
-                         "%.1f s wall" % (ns, cwall)}
+    t0 = time.time()
 
-    line = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "decryptions/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic (seeded keys and messages)",
-        "config": {"workload": "rsa2048-crt-decrypt", "keys": len(wl.keys), "messages": args.count,
-                   "modulus_bits": 32 * L, "window_bits": plan.window_bits,
-                   "lanes_per_op": plan.lanes_per_op, "wall_s": wall},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(line), flush=True)
+    if args.workload in ("crt2048", "enc2048"):
+        count = args.count or 16384
+        wl = W.workload_c3(count=count)
+        L, h = wl.limbs, wl.limbs // 2
+        print("# workload ready in %.1fs" % (time.time() - t0), file=sys.stderr, flush=True)
+        n_h, e_h, d_h = tab(wl, "n", L), tab(wl, "e", L), tab(wl, "d", L)
+        if args.workload == "crt2048":
+            c = dev(wl.ctxt)
+            p, q, dp, dq, qi = (dev(tab(wl, a, h)) for a in ("p", "q", "dp", "dq", "qinv"))
+            out = torch.empty_like(c)
+            plan = rsagpu.get_plan(h, 1)
+            ms, wall = timed(lambda: rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out), args.steps, args.warmup,
+                             torch)
+            # round trip on a spread of elements before reporting
+            idx = torch.arange(0, count, max(1, count // 64), device="cuda")
+            back = rsagpu.modexp(out[idx].contiguous(), dev(e_h)[idx].contiguous(), dev(n_h)[idx].contiguous())
+            if not torch.equal(back, c[idx]):
+                raise SystemExit("round-trip check failed")
+            products = sum(crt_products(wl.keys[k], plan.window_bits) for k in wl.key_of.tolist())
+            line.update(metric=METRIC, unit="decryptions/s",
+                        config={"workload": "rsa2048-crt-decrypt", "keys": len(wl.keys), "messages": count,
+                                "modulus_bits": 32 * L, "radix_bits": plan.radix_bits,
+                                "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
+            line["roofline"] = roofline(products, ms, "k_crt<%d,%d,%d>" % (plan.padded_limbs, plan.lanes_per_op,
+                                                                           plan.radix_bits))
+            if args.cpu_sample:
+                import oracle
+                cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32),
+                                   min(args.cpu_sample, count), "decryptions/s",
+                                   "plain C^d mod n (no CRT)")
+        else:
+            m = dev(wl.msgs)
+            e, n = dev(e_h), dev(n_h)
+            out = torch.empty_like(m)
+            plan = rsagpu.get_plan(L, 0)
+            ms, wall = timed(lambda: rsagpu.modexp(m, e, n, out=out), args.steps, args.warmup, torch)
+            products = sum(modexp_products(wl.keys[k], 17, plan.window_bits) for k in wl.key_of.tolist())
+            line.update(metric="2048-bit modexp/sec (encrypt, e=65537) on 1 GPU", unit="encryptions/s",
+                        config={"workload": "rsa2048-encrypt", "keys": len(wl.keys), "messages": count,
+                                "radix_bits": plan.radix_bits, "window_bits": plan.window_bits,
+                                "lanes_per_op": plan.lanes_per_op})
+            line["roofline"] = roofline(products, ms, "k_modexp<%d,%d,%d>" % (plan.padded_limbs, plan.lanes_per_op,
+                                                                              plan.radix_bits))
+            if args.cpu_sample:
+                import oracle
+                cpu = cpu_baseline(oracle, wl.msgs, e_h, n_h, out.cpu().numpy().view(np.uint32),
+                                   min(args.cpu_sample * 64, count), "encryptions/s", "m^65537 mod n")
+        value = count / (ms / 1e3)
+
+    elif args.workload in ("rsa64", "rsa1024"):
+        wl = W.workload_c1() if args.workload == "rsa64" else W.workload_c2()
+        count = len(wl.ctxt)
+        L = wl.limbs
+        n_h, d_h = tab(wl, "n", L), tab(wl, "d", L)
+        c, d, n = dev(wl.ctxt), dev(d_h), dev(n_h)
+        out = torch.empty_like(c)
+        plan = rsagpu.get_plan(L, 0)
+        ms, wall = timed(lambda: rsagpu.modexp(c, d, n, out=out), args.steps, args.warmup, torch)
+        products = sum(modexp_products(wl.keys[k], wl.keys[k].d.bit_length(), plan.window_bits)
+                       for k in wl.key_of.tolist())
+        line.update(metric="%d-bit modexp/sec (full-d decrypt) on 1 GPU" % (32 * L), unit="decryptions/s",
+                    config={"workload": wl.name + "-decrypt", "messages": count, "radix_bits": plan.radix_bits,
+                            "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
+        line["roofline"] = roofline(products, ms, "k_modexp<%d,%d,%d>" % (plan.padded_limbs, plan.lanes_per_op,
+                                                                          plan.radix_bits))
+        if args.cpu_sample:
+            import oracle
+            cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32),
+                               min(args.cpu_sample * (16 if L <= 2 else 2), count), "decryptions/s",
+                               "plain C^d mod n")
+        value = count / (ms / 1e3)
+
+    elif args.workload == "mixed":
+        wl = W.workload_c4()
+        nops = len(wl.kinds)
+        ks = rsagpu.KeySet(len(wl.keys))
+        for k in wl.keys:
+            ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
+        ops = rsagpu.pack_ops(wl.kinds, wl.key_ids, wl.in_offs, wl.in_offs).cuda()
+        inp = dev(wl.in_pool)
+        out = torch.zeros(wl.out_words, dtype=torch.int32, device="cuda")
+        ws = torch.empty(rsagpu.ops_workspace_size(nops), dtype=torch.uint8, device="cuda")
+        ms, wall = timed(lambda: rsagpu.ops_batch(ks, ops, inp, out, ws), args.steps, args.warmup, torch)
+        back = torch.zeros_like(out)
+        ops_inv = rsagpu.pack_ops(1 - wl.kinds, wl.key_ids, wl.in_offs, wl.in_offs).cuda()
+        rsagpu.ops_batch(ks, ops_inv, out, back, ws)
+        torch.cuda.synchronize()
+        if not torch.equal(back, inp) or rsagpu.device_errors() != 0:
+            raise SystemExit("mixed batch round trip failed")
+        products = 0
+        for kind, kid in zip(wl.kinds.tolist(), wl.key_ids.tolist()):
+            k = wl.keys[kid]
+            pl = rsagpu.get_plan(k.limbs // 2 if kind else k.limbs, kind)
+            products += crt_products(k, pl.window_bits) if kind else modexp_products(k, 17, pl.window_bits)
+        line.update(metric="mixed-size RSA ops/sec (1024-4096-bit, half CRT decrypt) on 1 GPU", unit="ops/s",
+                    config={"workload": wl.name, "ops": nops, "keys": len(wl.keys)})
+        line["roofline"] = roofline(products, ms, "k_ops_* (all buckets)")
+        value = nops / (ms / 1e3)
+        ks.close()
+
+    else:   # serve
+        from paper_1407_1465_amd.serve import GpuExecutor, Server, poisson_requests
+        keys = W.make_keys(2048, W.SEED_BASE + 5, 256) + W.make_keys(4096, W.SEED_BASE + 5, 64)
+        ks = rsagpu.KeySet(len(keys))
+        for k in keys:
+            ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
+        limbs = [k.limbs for k in keys]
+        mods = [k.n for k in keys]
+        pool, max_ops = 1 << 23, 1 << 16
+        ex = GpuExecutor(ks, limbs, pool, max_ops)
+
+        def run(reqs):
+            srv = Server(ex, pool, max_inflight=2, max_ops=max_ops)
+            srv.run(reqs)
+            return srv.stats()
+        # saturated rate: a closed burst
+        sat = run(poisson_requests(0.0, 400, W.SEED_BASE + 50, limbs, mods))
+        rate = 0.7 * sat["requests_per_s"]
+        nreq = max(200, int(rate * args.serve_seconds))
+        st = run(poisson_requests(rate, nreq, W.SEED_BASE + 51, limbs, mods))
+        if st["errors"] or rsagpu.device_errors():
+            raise SystemExit("serving run reported errors")
+        line.update(metric="RSA serving (2048/4096-bit keys, 70% CRT decrypt): requests/s at p50/p99 latency",
+                    unit="requests/s",
+                    config={"workload": "rsa-serve-2048-4096", "keys": len(keys), "rate_req_per_s": rate,
+                            "saturated_req_per_s": sat["requests_per_s"], "requests": st["requests"]})
+        line["latency_ms"] = {"p50": st["p50_ms"], "p99": st["p99_ms"], "mean": st["mean_ms"]}
+        line["ops_per_s"] = st["ops_per_s"]
+        value = st["requests_per_s"]
+        ms, wall = st["span_s"] * 1e3, st["span_s"]
+        ks.close()
+
+    line["value"] = value
+    line["ms_per_step"] = ms
+    line["config"]["wall_s"] = wall
+    line["cpu_baseline"] = cpu
+    order = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+             "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"]
+    out_line = {k: line[k] for k in order if k in line}
+    out_line.update({k: v for k, v in line.items() if k not in out_line})
+    print(json.dumps(out_line), flush=True)
 
 
 if __name__ == "__main__":

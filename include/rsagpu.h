@@ -65,7 +65,7 @@ typedef enum {
  * out may be the same buffer as base; other overlap is undefined.
  * 1 <= limbs <= RSA_MAX_LIMBS; count == 0 is a no-op returning RSA_OK.
  * Montgomery constants are derived per element on the device; for many
- * messages under one key prefer the resident-key entry points below.
+ * messages under one key prefer the resident-key entry points (keyset).
  */
 int rsa_modexp_batch(const uint32_t *base, const uint32_t *exp, const uint32_t *mod,
                      uint32_t *out, size_t count, int limbs, hipStream_t stream);
@@ -128,6 +128,59 @@ int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int wind
  * call into a HIP graph.
  */
 int rsa_init(void);
+
+/* ---- resident keys and mixed batches ------------------------------------
+ *
+ * A keyset holds RSA keys on the device together with their Montgomery
+ * constants (R mod m and R^2 mod m of n, p and q in every limb radix the
+ * kernels use), computed once when a key is added, so an operation starts
+ * directly with its exponentiation.  A batch is a device array of operation
+ * descriptors over keys of any sizes, run by one call: the operations are
+ * sorted on the device into buckets of one width class and kind, and each
+ * bucket is served by a persistent kernel whose waves claim operations from
+ * an atomic counter until the bucket is empty (largest classes first).
+ */
+typedef struct rsa_keyset rsa_keyset;
+
+typedef struct {
+    uint32_t kind;      /* 0: out = in^e mod n; 1: out = in^d mod n by CRT  */
+    int32_t key_id;     /* from rsa_keyset_add                               */
+    uint64_t in_off;    /* word offset of the input (the key's limbs words)  */
+    uint64_t out_off;   /* word offset of the output (same width)            */
+} rsa_op;
+
+/* Creates an empty keyset for up to max_keys keys on the current device.
+ * Allocates the keyset's device memory once (~6.7 KB per key). */
+int rsa_keyset_create(rsa_keyset **ks, int max_keys);
+
+/*
+ * Adds a key (HOST pointers, synchronous): n and e have `limbs` words,
+ * p, q, dp, dq, qinv have limbs/2 words; limbs even, 2 <= limbs <= 128.
+ * Checks n odd, p > q, p and q odd, n = p*q and e != 0 (RSA_EKEY otherwise),
+ * uploads the material and computes the Montgomery constants on the device.
+ * Not safe concurrently with rsa_ops_batch on the same keyset.
+ */
+int rsa_keyset_add(rsa_keyset *ks, int limbs, const uint32_t *n, const uint32_t *e, const uint32_t *p,
+                   const uint32_t *q, const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,
+                   int32_t *key_id);
+
+/* Frees the keyset (synchronises the device first). */
+int rsa_keyset_destroy(rsa_keyset *ks);
+
+/* Bytes of workspace rsa_ops_batch needs for up to max_ops operations. */
+size_t rsa_ops_workspace_size(size_t max_ops);
+
+/*
+ * Runs nops operations (device array `ops`) against the keyset: for each op,
+ * out_pool[out_off ..] = in_pool[in_off ..]^(e or d) mod n of its key, each
+ * range the key's limbs words; the input must be < n.  in_words / out_words
+ * bound the pools: an operation whose kind, key id or ranges are invalid is
+ * skipped and counted as a data error.  workspace: caller-owned device
+ * memory of at least rsa_ops_workspace_size(nops) bytes; calls that overlap
+ * in time must use different workspaces.  Asynchronous on `stream`.
+ */
+int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, const uint32_t *in_pool, size_t in_words,
+                  uint32_t *out_pool, size_t out_words, void *workspace, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Number of per-element data errors counted on the current device since the

@@ -1,0 +1,302 @@
+// Resident keys and mixed batches of operations (host side + bucketing).
+#include "../../include/rsagpu.h"
+#include "keyset_kernels.hpp"
+#include "registry.hpp"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+
+namespace rsagpu {
+
+static_assert(sizeof(OpDesc) == sizeof(rsa_op), "rsa_op layout");
+
+static const int kMaxBuckets = 32;            // 2 kinds x width classes
+static const size_t kWsHeader = 2 * kMaxBuckets * sizeof(unsigned);
+
+// ---- bucketing kernels -------------------------------------------------------
+
+__global__ void k_bucket_clear(unsigned *hdr)
+{
+    const int t = threadIdx.x;
+    if (t < 2 * kMaxBuckets) hdr[t] = 0u;
+}
+
+// Sorts operations into buckets (width class of the key, kind).  Invalid
+// operations (kind, key id, or an input/output range outside its pool) are
+// counted as data errors and dropped.
+__global__ void k_bucket_fill(const OpDesc *__restrict__ ops, unsigned long long nops,
+                              const KeyDev *__restrict__ keys, int nkeys, unsigned long long in_words,
+                              unsigned long long out_words, unsigned *counts, unsigned *lists,
+                              unsigned long long cap, unsigned long long *errs)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nops) return;
+    const OpDesc op = ops[i];
+    bool ok = op.kind <= 1u && op.key_id >= 0 && op.key_id < nkeys;
+    int b = 0;
+    if (ok) {
+        const KeyDev &k = keys[op.key_id];
+        const unsigned long long wds = (unsigned long long)k.words;
+        ok = op.in_off <= in_words && wds <= in_words - op.in_off && op.out_off <= out_words &&
+             wds <= out_words - op.out_off;
+        b = k.cls * 2 + (int)op.kind;
+    }
+    if (!ok) {
+        atomicAdd(errs, 1ull);
+        return;
+    }
+    const unsigned slot = atomicAdd(&counts[b], 1u);
+    lists[(unsigned long long)b * cap + slot] = (unsigned)i;
+}
+
+// ---- the keyset ------------------------------------------------------------------
+
+struct KeyHostInfo {
+    int cls;
+    int hcls;
+};
+
+}  // namespace rsagpu
+
+struct rsa_keyset {
+    int device;
+    int max_keys;
+    int nkeys;
+    size_t key_words;               // device words reserved per key
+    uint32_t *blob;                 // key material and constants
+    rsagpu::KeyDev *keys;           // device table
+    const uint32_t **stage_mods;    // setup staging (device)
+    int *stage_words;
+    rsagpu::ModConsts *stage_outs;
+    rsagpu::KeyHostInfo *info;      // host copy per key
+    unsigned class_mask;            // width classes present
+    std::mutex mu;
+};
+
+namespace rsagpu {
+
+static size_t s_for(int cls, int B) { return B == 32 ? (size_t)class_width(cls) : (size_t)class_s29(cls); }
+
+// Device words one key of class cls (n of `class_width` words) may need.
+static size_t key_words_for(int cls, int hcls)
+{
+    const size_t W = (size_t)class_width(cls), H = (size_t)class_width(hcls);
+    size_t w = 2 * W + 5 * H;                                         // n, e, p, q, dp, dq, qinv
+    for (int B : {32, 29}) w += 2 * s_for(cls, B) + 4 * s_for(hcls, B);  // one, r2 of n, p, q
+    return w;
+}
+
+static bool host_gt(const uint32_t *a, const uint32_t *b, int words)
+{
+    for (int i = words - 1; i >= 0; --i)
+        if (a[i] != b[i]) return a[i] > b[i];
+    return false;
+}
+
+// n == p * q for p, q of h words and n of 2h words (schoolbook product).
+static bool host_is_product(const uint32_t *n, const uint32_t *p, const uint32_t *q, int h)
+{
+    uint32_t *t = new (std::nothrow) uint32_t[2 * h]();
+    if (!t) return false;
+    for (int j = 0; j < h; ++j) {
+        uint64_t c = 0;
+        for (int i = 0; i < h; ++i) {
+            const uint64_t v = (uint64_t)p[i] * q[j] + t[i + j] + c;
+            t[i + j] = (uint32_t)v;
+            c = v >> 32;
+        }
+        t[j + h] = (uint32_t)c;
+    }
+    const bool eq = memcmp(t, n, sizeof(uint32_t) * 2 * h) == 0;
+    delete[] t;
+    return eq;
+}
+
+static bool any_nonzero(const uint32_t *x, int words)
+{
+    for (int i = 0; i < words; ++i)
+        if (x[i]) return true;
+    return false;
+}
+
+}  // namespace rsagpu
+
+using namespace rsagpu;
+
+extern "C" int rsa_keyset_create(rsa_keyset **out, int max_keys)
+{
+    if (!out || max_keys <= 0 || max_keys > (1 << 20)) return RSA_EINVAL;
+    *out = nullptr;
+    unsigned long long *errs = nullptr;
+    int st = device_state(&errs);
+    if (st != RSA_OK) return st;
+    rsa_keyset *ks = new (std::nothrow) rsa_keyset();
+    if (!ks) return RSA_ENOMEM;
+    (void)hipGetDevice(&ks->device);
+    ks->max_keys = max_keys;
+    const int top = num_classes() - 1;
+    ks->key_words = key_words_for(top, class_index(class_width(top) / 2));
+    hipError_t e = hipMalloc(&ks->blob, ks->key_words * sizeof(uint32_t) * (size_t)max_keys);
+    if (e == hipSuccess) e = hipMalloc(&ks->keys, sizeof(KeyDev) * (size_t)max_keys);
+    if (e == hipSuccess) e = hipMalloc(&ks->stage_mods, sizeof(uint32_t *) * 4);
+    if (e == hipSuccess) e = hipMalloc(&ks->stage_words, sizeof(int) * 4);
+    if (e == hipSuccess) e = hipMalloc(&ks->stage_outs, sizeof(ModConsts) * 4);
+    ks->info = new (std::nothrow) KeyHostInfo[max_keys];
+    if (e != hipSuccess || !ks->info) {
+        rsa_keyset_destroy(ks);
+        return e == hipSuccess ? RSA_ENOMEM : status_of(e);
+    }
+    *out = ks;
+    return RSA_OK;
+}
+
+extern "C" int rsa_keyset_destroy(rsa_keyset *ks)
+{
+    if (!ks) return RSA_OK;
+    (void)hipDeviceSynchronize();
+    if (ks->blob) (void)hipFree(ks->blob);
+    if (ks->keys) (void)hipFree(ks->keys);
+    if (ks->stage_mods) (void)hipFree(ks->stage_mods);
+    if (ks->stage_words) (void)hipFree(ks->stage_words);
+    if (ks->stage_outs) (void)hipFree(ks->stage_outs);
+    delete[] ks->info;
+    delete ks;
+    return RSA_OK;
+}
+
+extern "C" int rsa_keyset_add(rsa_keyset *ks, int limbs, const uint32_t *n, const uint32_t *e, const uint32_t *p,
+                              const uint32_t *q, const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,
+                              int32_t *key_id)
+{
+    if (!ks || !n || !e || !p || !q || !dp || !dq || !qinv || !key_id) return RSA_EINVAL;
+    if (limbs < 2 || limbs > RSA_MAX_LIMBS || (limbs & 1)) return RSA_ELIMBS;
+    const int h = limbs / 2;
+    // cheap consistency checks of the key material
+    if (!(n[0] & 1u) || !(p[0] & 1u) || !(q[0] & 1u) || !host_gt(p, q, h) || !any_nonzero(e, limbs) ||
+        !host_is_product(n, p, q, h) || (h == 1 && q[0] < 3u))
+        return RSA_EKEY;
+    std::lock_guard<std::mutex> lock(ks->mu);
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ks->device) return RSA_EINVAL;
+    if (ks->nkeys >= ks->max_keys) return RSA_ENOMEM;
+    const int id = ks->nkeys;
+    const int cls = class_index(limbs), hcls = class_index(h);
+    if (cls < 0 || hcls < 0) return RSA_ELIMBS;
+
+    // layout of this key's words in the blob
+    uint32_t *base = ks->blob + (size_t)id * ks->key_words;
+    const size_t W = (size_t)class_width(cls), Hw = (size_t)class_width(hcls);
+    KeyDev kd;
+    memset(&kd, 0, sizeof(kd));
+    kd.cls = cls;
+    kd.words = limbs;
+    kd.hwords = h;
+    uint32_t *cur = base;
+    auto take = [&](size_t words) { uint32_t *r = cur; cur += words; return r; };
+    uint32_t *dn = take(W), *de = take(W), *dpp = take(Hw), *dqq = take(Hw), *ddp = take(Hw), *ddq = take(Hw),
+             *dqi = take(Hw);
+    kd.n = dn; kd.e = de; kd.p = dpp; kd.q = dqq; kd.dp = ddp; kd.dq = ddq; kd.qinv = dqi;
+    for (int slot = 0; slot < 2; ++slot) {
+        const int B = slot == 0 ? 32 : 29;
+        const size_t sn = s_for(cls, B), sh = s_for(hcls, B);
+        kd.cn[slot] = ModConsts{sn ? take(sn) : nullptr, sn ? take(sn) : nullptr};
+        kd.cp[slot] = ModConsts{sh ? take(sh) : nullptr, sh ? take(sh) : nullptr};
+        kd.cq[slot] = ModConsts{sh ? take(sh) : nullptr, sh ? take(sh) : nullptr};
+    }
+    if ((size_t)(cur - base) > ks->key_words) return RSA_ELIMBS;
+
+    hipError_t err = hipSuccess;
+    auto put = [&](uint32_t *dst, const uint32_t *src, int words) {
+        if (err == hipSuccess) err = hipMemcpy(dst, src, sizeof(uint32_t) * words, hipMemcpyHostToDevice);
+    };
+    put(dn, n, limbs); put(de, e, limbs);
+    put(dpp, p, h); put(dqq, q, h); put(ddp, dp, h); put(ddq, dq, h); put(dqi, qinv, h);
+    if (err != hipSuccess) return status_of(err);
+
+    // Montgomery constants of n (class cls) and p, q (class hcls), each radix
+    for (int slot = 0; slot < 2; ++slot) {
+        const int B = slot == 0 ? 32 : 29;
+        struct Job { int c; const uint32_t *m; int words; ModConsts out; };
+        Job jobs[3] = {{cls, dn, limbs, kd.cn[slot]}, {hcls, dpp, h, kd.cp[slot]}, {hcls, dqq, h, kd.cq[slot]}};
+        for (const Job &j : jobs) {
+            if (!j.out.one) continue;
+            const Instance *in = any_instance(j.c, B);
+            if (!in) continue;
+            const uint32_t *mp = j.m;
+            err = hipMemcpy(ks->stage_mods, &mp, sizeof(mp), hipMemcpyHostToDevice);
+            if (err == hipSuccess) err = hipMemcpy(ks->stage_words, &j.words, sizeof(int), hipMemcpyHostToDevice);
+            if (err == hipSuccess) err = hipMemcpy(ks->stage_outs, &j.out, sizeof(ModConsts), hipMemcpyHostToDevice);
+            if (err == hipSuccess) err = in->setup(ks->stage_mods, ks->stage_words, ks->stage_outs, 1, nullptr);
+            if (err == hipSuccess) err = hipStreamSynchronize(nullptr);
+            if (err != hipSuccess) return status_of(err);
+        }
+    }
+    err = hipMemcpy(ks->keys + id, &kd, sizeof(kd), hipMemcpyHostToDevice);
+    if (err != hipSuccess) return status_of(err);
+    ks->info[id] = KeyHostInfo{cls, hcls};
+    ks->class_mask |= 1u << cls;
+    ks->nkeys = id + 1;
+    *key_id = id;
+    return RSA_OK;
+}
+
+extern "C" size_t rsa_ops_workspace_size(size_t max_ops)
+{
+    return kWsHeader + (size_t)kMaxBuckets * max_ops * sizeof(unsigned);
+}
+
+extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, const uint32_t *in_pool,
+                             size_t in_words, uint32_t *out_pool, size_t out_words, void *workspace,
+                             size_t ws_bytes, hipStream_t stream)
+{
+    if (!ks) return RSA_EINVAL;
+    if (nops == 0) return RSA_OK;
+    if (!ops || !in_pool || !out_pool || !workspace || ws_bytes < rsa_ops_workspace_size(nops)) return RSA_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ks->device) return RSA_EINVAL;
+    unsigned long long *errs = nullptr;
+    int st = device_state(&errs);
+    if (st != RSA_OK) return st;
+    const size_t cap = (ws_bytes - kWsHeader) / ((size_t)kMaxBuckets * sizeof(unsigned));
+    unsigned *hdr = static_cast<unsigned *>(workspace);
+    unsigned *counts = hdr, *counters = hdr + kMaxBuckets, *lists = hdr + 2 * kMaxBuckets;
+    int nkeys;
+    unsigned mask;
+    {
+        std::lock_guard<std::mutex> lock(ks->mu);
+        nkeys = ks->nkeys;
+        mask = ks->class_mask;
+    }
+    hipLaunchKernelGGL(k_bucket_clear, dim3(1), dim3(64), 0, stream, hdr);
+    hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)((nops + 255) / 256)), dim3(256), 0, stream,
+                       reinterpret_cast<const OpDesc *>(ops), (unsigned long long)nops, ks->keys, nkeys,
+                       (unsigned long long)in_words, (unsigned long long)out_words, counts, lists,
+                       (unsigned long long)cap, errs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return status_of(e);
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 1;
+    // most expensive buckets first: wide classes, decryptions before encryptions
+    for (int cls = num_classes() - 1; cls >= 0; --cls) {
+        if (!(mask & (1u << cls))) continue;
+        for (int kind = 1; kind >= 0; --kind) {
+            const int b = cls * 2 + kind;
+            const int width = kind == 0 ? class_width(cls) : class_width(cls) / 2;
+            Resolved r;
+            if (!resolve(width, kind, &r)) return RSA_ELIMBS;
+            int per = r.inst->blocks_per_cu(kind, r.w);
+            if (per <= 0) per = 1;
+            const int blocks = per * cus;
+            const ops_launcher fn = kind == 0 ? r.inst->ops_enc : r.inst->ops_crt;
+            e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b,
+                   counters + b, in_pool, out_pool, r.w, blocks, stream);
+            if (e != hipSuccess) return status_of(e);
+        }
+    }
+    return RSA_OK;
+}

@@ -1,0 +1,220 @@
+// Resident-key kernels: Montgomery-constant setup for a key, and persistent
+// per-bucket kernels that run a batch of operation descriptors.
+//
+// A key is held on the device as its raw 32-bit-word material (n, e, p, q,
+// dp, dq, qinv) plus, for each limb radix the library computes in, the
+// Montgomery constants one = R mod m and r2 = R^2 mod m of m = n, p and q,
+// stored as the kernel's limbs.  They are computed once when the key is added,
+// so an operation starts directly with its exponentiation.
+//
+// Operations are grouped on the device into buckets of one (width class,
+// kind); each bucket is served by a persistent kernel whose waves claim
+// NG operations at a time from an atomic counter until the bucket is empty.
+#pragma once
+
+#include "modexp_kernels.hpp"
+
+namespace rsagpu {
+
+// Constants of one modulus in one radix: `one` and `r2`, S limbs each.
+struct ModConsts {
+    uint32_t *one;
+    uint32_t *r2;
+};
+
+// Device view of one resident key.
+struct KeyDev {
+    int cls;                  // width class index
+    int words;                // 32-bit words of n
+    int hwords;               // 32-bit words of p and q
+    int pad;
+    const uint32_t *n, *e, *p, *q, *dp, *dq, *qinv;
+    ModConsts cn[2], cp[2], cq[2];     // [0]: radix 2^32, [1]: radix 2^29
+};
+
+// One operation descriptor (layout shared with include/rsagpu.h rsa_op).
+struct OpDesc {
+    uint32_t kind;            // 0: in^e mod n, 1: CRT decryption
+    int32_t key_id;
+    unsigned long long in_off, out_off;
+};
+
+template <int B>
+__device__ __forceinline__ int radix_slot() { return B == 32 ? 0 : 1; }
+
+// Loads limbs [r*L, r*L+L) of an S-limb array of kernel limbs.
+template <int S, int G>
+__device__ __forceinline__ void load_raw(uint32_t (&x)[S / G], const uint32_t *p, bool live)
+{
+    constexpr int L = S / G;
+    const int r = grp_lane<G>();
+#pragma unroll
+    for (int k = 0; k < L; ++k) x[k] = live ? p[r * L + k] : 0u;
+}
+
+template <int S, int G>
+__device__ __forceinline__ void store_raw(uint32_t *p, const uint32_t (&x)[S / G], bool live)
+{
+    constexpr int L = S / G;
+    const int r = grp_lane<G>();
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < L; ++k) p[r * L + k] = x[k];
+}
+
+// Constants of `count` moduli (32-bit words each at mods[i]): one, r2 in
+// radix 2^B with S limbs, written to outs[i] (the caller validated the moduli).
+template <int S, int G, int B>
+__global__ __launch_bounds__(64) void k_setup(const uint32_t *const *mods, const int *words, ModConsts *outs,
+                                              int count)
+{
+    using Ar = Arith<S, G, B>;
+    using Ly = Layout<S, G>;
+    constexpr int L = S / G, NG = 64 / G;
+    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
+    const int g = grp_index<G>();
+    const int i = blockIdx.x * NG + g;
+    const bool live = i < count;
+    uint32_t n[L];
+    Ar::load(n, live ? mods[i] : nullptr, live ? words[i] : 0, 0, live);
+    const uint32_t n0 = grp_bcast0<G>(n[0]);
+    const uint32_t bl = Ar::bitlen(n);
+    const bool valid = live && (n0 & 1u) && bl > 1;
+    const uint32_t n0inv = Ar::n0inv(n0 | 1u);
+    uint32_t one[L], r2[L];
+    mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds, lds + Ly::WORDS);
+    if (live) {
+        store_raw<S, G>(outs[i].one, one, true);
+        store_raw<S, G>(outs[i].r2, r2, true);
+    }
+}
+
+// Claims the next chunk of `n` operations of a bucket for this wave.
+__device__ __forceinline__ unsigned claim(unsigned *counter, unsigned n)
+{
+    unsigned base = 0;
+    if (lane_id() == 0) base = atomicAdd(counter, n);
+    return (unsigned)__builtin_amdgcn_readfirstlane((int)base);
+}
+
+// Bucket of encryptions (in^e mod n) for keys of one width class: S limbs of
+// radix 2^B hold n.
+template <int S, int G, int B>
+__global__ __launch_bounds__(64) void k_ops_enc(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
+                                                const unsigned *__restrict__ list, const unsigned *count_p,
+                                                unsigned *counter, const uint32_t *__restrict__ in_pool,
+                                                uint32_t *out_pool, int w)
+{
+    using Ar = Arith<S, G, B>;
+    constexpr int L = S / G, NG = 64 / G;
+    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
+    const int g = grp_index<G>();
+    const unsigned count = *count_p;
+    for (;;) {
+        const unsigned base = claim(counter, NG);
+        if (base >= count) break;                     // wave-uniform exit
+        const unsigned idx = base + g;
+        const bool live = idx < count;
+        const OpDesc op = ops[live ? list[idx] : list[base]];
+        const KeyDev &k = keys[op.key_id];
+        const ModConsts &mc = k.cn[radix_slot<B>()];
+        uint32_t n[L], x[L], one[L], r2[L], xt[L], A[L];
+        Ar::load(n, k.n, k.words, 0, live);
+        Ar::load(x, in_pool + op.in_off, k.words, 0, live);
+        load_raw<S, G>(one, mc.one, live);
+        load_raw<S, G>(r2, mc.r2, live);
+        const uint32_t n0inv = Ar::n0inv(grp_bcast0<G>(n[0]) | 1u);
+        mont_mul_reg<S, G, B>(xt, x, r2, lds, n, n0inv);
+        group_modexp<S, G, B>(A, xt, k.e, k.words, live, n, n0inv, one, lds, w);
+        from_mont<S, G, B>(A, lds, n, n0inv);
+        store_words<S, G, B>(out_pool + op.out_off, A, k.words, live, true, lds);
+    }
+}
+
+// Bucket of CRT decryptions for keys of one width class: H limbs of radix
+// 2^B hold p and q; two groups (p, q) per operation.
+template <int H, int G, int B>
+__global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
+                                                const unsigned *__restrict__ list, const unsigned *count_p,
+                                                unsigned *counter, const uint32_t *__restrict__ in_pool,
+                                                uint32_t *out_pool, int w)
+{
+    using Ar = Arith<H, G, B>;
+    using Ly = Layout<H, G>;
+    constexpr int L = H / G, NG = 64 / G, NP = NG / 2;
+    static_assert(NG >= 2, "a wave holds at least one pair of groups");
+    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
+    const int g = grp_index<G>(), r = grp_lane<G>();
+    const int half = g & 1;
+    const unsigned count = *count_p;
+    for (;;) {
+        const unsigned base = claim(counter, NP);
+        if (base >= count) break;
+        const unsigned idx = base + (g >> 1);
+        const bool live = idx < count;
+        const OpDesc op = ops[live ? list[idx] : list[base]];
+        const KeyDev &k = keys[op.key_id];
+        const int hl = k.hwords, full = 2 * hl;
+        const ModConsts &mc = half ? k.cq[radix_slot<B>()] : k.cp[radix_slot<B>()];
+        uint32_t n[L], other[L], clo[L], chi[L], one[L], r2[L], r3[L];
+        Ar::load(n, half ? k.q : k.p, hl, 0, live);
+        Ar::load(other, half ? k.p : k.q, hl, 0, live);
+        Ar::load(clo, in_pool + op.in_off, full, 0, live);
+        Ar::load(chi, in_pool + op.in_off, full, B * H, live);
+        load_raw<H, G>(one, mc.one, live);
+        load_raw<H, G>(r2, mc.r2, live);
+        const uint32_t n0inv = Ar::n0inv(grp_bcast0<G>(n[0]) | 1u);
+        mont_mul_reg<H, G, B>(r3, r2, r2, lds, n, n0inv);
+        uint32_t xt[L], t2[L];
+        mont_mul_reg<H, G, B>(xt, clo, r2, lds, n, n0inv);
+        mont_mul_reg<H, G, B>(t2, chi, r3, lds, n, n0inv);
+        {
+            const uint32_t ovf = Ar::add(xt, t2);
+            Ar::cond_sub(xt, ovf, n);
+        }
+        uint32_t A[L];
+        group_modexp<H, G, B>(A, xt, half ? k.dq : k.dp, hl, live, n, n0inv, one, lds, w);
+        from_mont<H, G, B>(A, lds, n, n0inv);
+
+        uint32_t mq[L], qv[L], hh[L];
+        lds_sync();
+        lds_put<H, G>(lds, A);
+        lds_sync();
+        lds_get<H, G>(mq, lds, g ^ 1);
+        {
+            uint32_t d[L], e[L];
+            const uint32_t neg = Ar::sub(d, A, mq);
+#pragma unroll
+            for (int j = 0; j < L; ++j) e[j] = d[j];
+            Ar::add(e, n);
+#pragma unroll
+            for (int j = 0; j < L; ++j) A[j] = neg ? e[j] : d[j];
+        }
+        Ar::load(qv, k.qinv, hl, 0, live && !half);
+        mont_mul_reg<H, G, B>(qv, qv, r2, lds, n, n0inv);
+        mont_mul_reg<H, G, B>(hh, A, qv, lds, n, n0inv);
+        lds_sync();
+        lds_put<H, G>(lds, hh);
+        lds_sync();
+        uint32_t *stage = lds + Ly::WORDS + g * (2 * H);
+        auto sink = [&](int i, uint32_t v) {
+            if (r == 0) stage[i] = v;
+        };
+        uint32_t high[L];
+        Ar::mul_wide(high, mq, other, lds, sink);
+#pragma unroll
+        for (int j = 0; j < L; ++j) stage[H + r * L + j] = high[j];
+        lds_sync();
+        if (live && !half) {
+            uint32_t *o = out_pool + op.out_off;
+            if constexpr (B == 32) {
+                for (int wd = r; wd < full; wd += G) o[wd] = stage[wd];
+            } else {
+                for (int wd = r; wd < full; wd += G) o[wd] = rword<B>(stage, 2 * H, wd);
+            }
+        }
+        lds_sync();
+    }
+}
+
+}  // namespace rsagpu

@@ -16,6 +16,20 @@ typedef hipError_t (*crt_launcher)(const uint32_t *c, const uint32_t *p, const u
                                    const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count, int hl,
                                    int w, unsigned long long *errs, hipStream_t stream);
 
+struct KeyDev;
+struct ModConsts;
+struct OpDesc;
+
+typedef hipError_t (*setup_launcher)(const uint32_t *const *mods, const int *words, ModConsts *outs, int count,
+                                     hipStream_t stream);
+// Persistent bucket kernel: `blocks` workgroups claim operations until the
+// bucket (list, *count) is exhausted.
+typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const unsigned *list,
+                                   const unsigned *count, unsigned *counter, const uint32_t *in_pool,
+                                   uint32_t *out_pool, int w, int blocks, hipStream_t stream);
+// Workgroups of an ops kernel resident per CU at window w (occupancy query).
+typedef int (*ops_occupancy)(int kind, int w);
+
 // LDS bytes of one 64-lane workgroup: 2^w operand buffers of S * (64 / G) words.
 inline size_t lds_bytes_for(int S, int G, int w) { return (size_t)(1u << w) * (size_t)S * (size_t)(64 / G) * 4u; }
 
@@ -27,5 +41,22 @@ template <int H, int G, int B>
 hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
                       const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count, int hl, int w,
                       unsigned long long *errs, hipStream_t stream);
+
+template <int S, int G, int B>
+hipError_t launch_setup(const uint32_t *const *mods, const int *words, ModConsts *outs, int count,
+                        hipStream_t stream);
+
+template <int S, int G, int B>
+hipError_t launch_ops_enc(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
+                          unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
+                          hipStream_t stream);
+
+template <int S, int G, int B>
+hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
+                          unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
+                          hipStream_t stream);
+
+template <int S, int G, int B>
+int ops_blocks_per_cu(int kind, int w);
 
 }  // namespace rsagpu

@@ -2,7 +2,7 @@
 #pragma once
 
 #include "launch.hpp"
-#include "modexp_kernels.hpp"
+#include "keyset_kernels.hpp"
 
 namespace rsagpu {
 
@@ -29,6 +29,48 @@ hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, c
     return hipGetLastError();
 }
 
+template <int S, int G, int B>
+hipError_t launch_setup(const uint32_t *const *mods, const int *words, ModConsts *outs, int count,
+                        hipStream_t stream)
+{
+    const int ng = 64 / G;
+    const int blocks = (count + ng - 1) / ng;
+    hipLaunchKernelGGL((k_setup<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, 2), stream, mods, words,
+                       outs, count);
+    return hipGetLastError();
+}
+
+template <int S, int G, int B>
+hipError_t launch_ops_enc(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
+                          unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
+                          hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_ops_enc<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, w), stream, keys, ops,
+                       list, count, counter, in_pool, out_pool, w);
+    return hipGetLastError();
+}
+
+template <int S, int G, int B>
+hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
+                          unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
+                          hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, w), stream, keys, ops,
+                       list, count, counter, in_pool, out_pool, w);
+    return hipGetLastError();
+}
+
+template <int S, int G, int B>
+int ops_blocks_per_cu(int kind, int w)
+{
+    int nb = 0;
+    const size_t lds = lds_bytes_for(S, G, w);
+    hipError_t e = kind == 0
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_enc<S, G, B>), 64, lds)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B>), 64, lds);
+    return e == hipSuccess ? nb : 0;
+}
+
 }  // namespace rsagpu
 
 #define RSAGPU_INSTANTIATE(B_, S_, G_)                                                                      \
@@ -38,4 +80,13 @@ hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, c
     template hipError_t rsagpu::launch_crt<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *,    \
                                                    const uint32_t *, const uint32_t *, const uint32_t *,    \
                                                    uint32_t *, size_t, int, int, unsigned long long *,      \
-                                                   hipStream_t);
+                                                   hipStream_t);                                            \
+    template hipError_t rsagpu::launch_setup<S_, G_, B_>(const uint32_t *const *, const int *,              \
+                                                         rsagpu::ModConsts *, int, hipStream_t);            \
+    template hipError_t rsagpu::launch_ops_enc<S_, G_, B_>(                                                 \
+        const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
+        const uint32_t *, uint32_t *, int, int, hipStream_t);                                               \
+    template hipError_t rsagpu::launch_ops_crt<S_, G_, B_>(                                                 \
+        const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
+        const uint32_t *, uint32_t *, int, int, hipStream_t);                                               \
+    template int rsagpu::ops_blocks_per_cu<S_, G_, B_>(int, int);

@@ -1,0 +1,42 @@
+// Host-side registry shared by the C-ABI translation units: kernel instances,
+// width classes, execution plans and per-device state.
+#pragma once
+
+#include "launch.hpp"
+
+namespace rsagpu {
+
+struct Instance {
+    int B;
+    int S;
+    int G;
+    modexp_launcher modexp;
+    crt_launcher crt;
+    setup_launcher setup;
+    ops_launcher ops_enc;
+    ops_launcher ops_crt;
+    int (*blocks_per_cu)(int kind, int w);
+};
+
+// Width classes in 32-bit limbs and their radix-2^29 limb counts.
+int num_classes();
+int class_width(int i);
+int class_s29(int i);
+int class_index(int limbs);
+
+// Instance of class i in radix 2^B with G lanes per exponentiation.
+const Instance *find_instance(int i, int B, int G);
+// Any instance of class i in radix 2^B (for work whose speed does not matter).
+const Instance *any_instance(int i, int B);
+
+struct Resolved {
+    const Instance *inst;
+    int w;
+};
+bool resolve(int limbs, int kind, Resolved *r);
+
+// Per-device data-error counter (allocated once per device).
+int device_state(unsigned long long **errs);
+int status_of(hipError_t e);
+
+}  // namespace rsagpu

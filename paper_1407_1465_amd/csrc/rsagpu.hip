@@ -1,7 +1,7 @@
 // Host side of librsagpu.so: argument checks, execution plans, per-device
 // state and launches.  No arithmetic happens here.
 #include "../../include/rsagpu.h"
-#include "launch.hpp"
+#include "registry.hpp"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -11,16 +11,10 @@
 
 namespace rsagpu {
 
-struct Instance {
-    int B;
-    int S;
-    int G;
-    modexp_launcher modexp;
-    crt_launcher crt;
-};
-
 static const Instance kInstances[] = {
-#define X(B_, S_, G_) {B_, S_, G_, &launch_modexp<S_, G_, B_>, &launch_crt<S_, G_, B_>},
+#define X(B_, S_, G_)                                                                                     \
+    {B_, S_, G_, &launch_modexp<S_, G_, B_>, &launch_crt<S_, G_, B_>, &launch_setup<S_, G_, B_>,          \
+     &launch_ops_enc<S_, G_, B_>, &launch_ops_crt<S_, G_, B_>, &ops_blocks_per_cu<S_, G_, B_>},
 #include "instances.def"
 #undef X
 };
@@ -68,14 +62,18 @@ static void init_plans()
         for (int i = 0; i < kNumClasses; ++i) g_plan[k][i].store(pack(kDefault[k][i]));
 }
 
-static int class_index(int limbs)
+int num_classes() { return kNumClasses; }
+int class_width(int i) { return kClasses[i]; }
+int class_s29(int i) { return kS29[i]; }
+
+int class_index(int limbs)
 {
     for (int i = 0; i < kNumClasses; ++i)
         if (kClasses[i] >= limbs) return i;
     return -1;
 }
 
-static const Instance *find_instance(int i, int B, int G)
+const Instance *find_instance(int i, int B, int G)
 {
     const int S = B == 32 ? kClasses[i] : (B == 29 ? kS29[i] : 0);
     if (S == 0) return nullptr;
@@ -84,12 +82,16 @@ static const Instance *find_instance(int i, int B, int G)
     return nullptr;
 }
 
-struct Resolved {
-    const Instance *inst;
-    int w;
-};
+const Instance *any_instance(int i, int B)
+{
+    const int S = B == 32 ? kClasses[i] : (B == 29 ? kS29[i] : 0);
+    if (S == 0) return nullptr;
+    for (const Instance &in : kInstances)
+        if (in.B == B && in.S == S) return &in;
+    return nullptr;
+}
 
-static bool resolve(int limbs, int kind, Resolved *r)
+bool resolve(int limbs, int kind, Resolved *r)
 {
     std::call_once(g_plan_once, init_plans);
     const int i = class_index(limbs);
@@ -106,7 +108,7 @@ static const int kMaxDevices = 64;
 static unsigned long long *g_errs[kMaxDevices];
 static std::mutex g_dev_mutex;
 
-static int device_state(unsigned long long **errs)
+int device_state(unsigned long long **errs)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RSA_EHIP;
@@ -125,7 +127,7 @@ static int device_state(unsigned long long **errs)
     return RSA_OK;
 }
 
-static int status_of(hipError_t e)
+int status_of(hipError_t e)
 {
     if (e == hipSuccess) return RSA_OK;
     if (e == hipErrorOutOfMemory) return RSA_ENOMEM;

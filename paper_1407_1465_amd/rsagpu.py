@@ -49,9 +49,26 @@ _lib.rsa_set_plan.restype = ctypes.c_int
 _lib.rsa_init.argtypes = []
 _lib.rsa_init.restype = ctypes.c_int
 
+_lib.rsa_keyset_create.argtypes = [ctypes.POINTER(_P), ctypes.c_int]
+_lib.rsa_keyset_create.restype = ctypes.c_int
+_U32P = ctypes.POINTER(ctypes.c_uint32)
+_lib.rsa_keyset_add.argtypes = [_P, ctypes.c_int] + [_U32P] * 7 + [ctypes.POINTER(ctypes.c_int32)]
+_lib.rsa_keyset_add.restype = ctypes.c_int
+_lib.rsa_keyset_destroy.argtypes = [_P]
+_lib.rsa_keyset_destroy.restype = ctypes.c_int
+_lib.rsa_ops_workspace_size.argtypes = [ctypes.c_size_t]
+_lib.rsa_ops_workspace_size.restype = ctypes.c_size_t
+_lib.rsa_ops_batch.argtypes = [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P,
+                               ctypes.c_size_t, _P]
+_lib.rsa_ops_batch.restype = ctypes.c_int
+
 # exported symbols, in the order include/rsagpu.h declares them
 EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_get_plan", "rsa_set_plan", "rsa_init",
-           "rsa_device_errors", "rsa_status_str", "rsa_version")
+           "rsa_keyset_create", "rsa_keyset_add", "rsa_keyset_destroy", "rsa_ops_workspace_size",
+           "rsa_ops_batch", "rsa_device_errors", "rsa_status_str", "rsa_version")
+
+OP_ENCRYPT = 0
+OP_DECRYPT_CRT = 1
 
 
 class RSAError(RuntimeError):
@@ -149,6 +166,84 @@ def device_errors(stream: Optional[torch.cuda.Stream] = None) -> int:
     v = ctypes.c_uint64(0)
     _check(_lib.rsa_device_errors(_stream_handle(stream), ctypes.byref(v)), "rsa_device_errors")
     return int(v.value)
+
+
+def _host_limbs(value: int, words: int):
+    arr = (ctypes.c_uint32 * words)()
+    for i in range(words):
+        arr[i] = (value >> (32 * i)) & 0xFFFFFFFF
+    return arr
+
+
+class KeySet:
+    """Resident keys on the current device (rsa_keyset_*)."""
+
+    def __init__(self, max_keys: int):
+        self._h = _P()
+        _check(_lib.rsa_keyset_create(ctypes.byref(self._h), max_keys), "rsa_keyset_create")
+        self.limbs = []
+
+    def add(self, limbs: int, n: int, e: int, p: int, q: int, dp: int, dq: int, qinv: int) -> int:
+        """Adds a key given as Python integers; returns its key id."""
+        h = limbs // 2
+        kid = ctypes.c_int32(-1)
+        args = [_host_limbs(n, limbs), _host_limbs(e, limbs)] + [_host_limbs(v, h) for v in (p, q, dp, dq, qinv)]
+        _check(_lib.rsa_keyset_add(self._h, limbs, *[ctypes.cast(a, _U32P) for a in args], ctypes.byref(kid)),
+               "rsa_keyset_add")
+        self.limbs.append(limbs)
+        return kid.value
+
+    def close(self) -> None:
+        if self._h:
+            _check(_lib.rsa_keyset_destroy(self._h), "rsa_keyset_destroy")
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def ops_workspace_size(max_ops: int) -> int:
+    return int(_lib.rsa_ops_workspace_size(max_ops))
+
+
+def ops_batch(ks: KeySet, ops: torch.Tensor, in_pool: torch.Tensor, out_pool: torch.Tensor,
+              workspace: torch.Tensor, nops: Optional[int] = None,
+              stream: Optional[torch.cuda.Stream] = None) -> None:
+    """Runs operation descriptors against a keyset (rsa_ops_batch).
+
+    ops: int64 device tensor (nops, 3) laid out as rsa_op: column 0 holds
+    kind | key_id << 32, columns 1 and 2 the input and output word offsets.
+    in_pool / out_pool: int32 device tensors of 32-bit words; workspace: a
+    device tensor of at least ops_workspace_size(nops) bytes."""
+    if ops.dtype != torch.int64 or ops.dim() != 2 or ops.shape[1] != 3 or not ops.is_contiguous():
+        raise ValueError("ops must be a contiguous (n, 3) int64 tensor")
+    n = ops.shape[0] if nops is None else nops
+    for name, t in (("ops", ops), ("in_pool", in_pool), ("out_pool", out_pool), ("workspace", workspace)):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous device tensor" % name)
+    _check(_lib.rsa_ops_batch(ks.handle, ops.data_ptr(), n, in_pool.data_ptr(), in_pool.numel(),
+                              out_pool.data_ptr(), out_pool.numel(), workspace.data_ptr(),
+                              workspace.numel() * workspace.element_size(), _stream_handle(stream)),
+           "rsa_ops_batch")
+
+
+def pack_ops(kinds, key_ids, in_offs, out_offs) -> torch.Tensor:
+    """Host int64 (n, 3) array in the rsa_op layout."""
+    import numpy as np
+    kinds = np.asarray(kinds, dtype=np.int64)
+    key_ids = np.asarray(key_ids, dtype=np.int64)
+    a = np.empty((len(kinds), 3), dtype=np.int64)
+    a[:, 0] = kinds | (key_ids << 32)
+    a[:, 1] = np.asarray(in_offs, dtype=np.int64)
+    a[:, 2] = np.asarray(out_offs, dtype=np.int64)
+    return torch.from_numpy(a)
 
 
 def version() -> int:

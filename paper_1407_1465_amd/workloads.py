@@ -367,3 +367,66 @@ def workload_c2(count: int = 65536) -> Workload:
 def workload_c3(count: int = 16384, nkeys: int = 64) -> Workload:
     """2048-bit moduli, 64 keys, messages round-robin; CRT decryption."""
     return single_size_workload("rsa2048-64keys", 2048, nkeys, count, SEED_BASE + 3)
+
+
+@dataclass
+class MixedWorkload:
+    """Operations over keys of several sizes, laid out for rsa_ops_batch."""
+    name: str
+    keys: List[RSAKey]          # key id = index
+    kinds: np.ndarray           # (nops,) 0 = encrypt, 1 = CRT decrypt
+    key_ids: np.ndarray         # (nops,)
+    in_offs: np.ndarray         # (nops,) word offsets into in_pool
+    in_pool: np.ndarray         # uint32 words: op i's input at in_offs[i] (its key's limbs words)
+    out_words: int              # size of the output pool (same offsets)
+
+
+def largest_remainder(total: int, weights: Sequence[int]) -> List[int]:
+    """Integer split of total proportional to weights (largest remainder)."""
+    s = sum(weights)
+    raw = [total * w / s for w in weights]
+    base = [int(math.floor(r)) for r in raw]
+    order = sorted(range(len(weights)), key=lambda i: raw[i] - base[i], reverse=True)
+    for i in order[:total - sum(base)]:
+        base[i] += 1
+    return base
+
+
+def mixed_workload(name: str, sizes: Sequence[int], weights: Sequence[int], total: int,
+                   keys_per_size: int, seed: int) -> MixedWorkload:
+    """Ops over `keys_per_size` keys of each size; within a size, even op
+    index = encryption and odd = CRT decryption, keys round-robin; inputs
+    uniform in [0, n); op order shuffled with a seeded permutation."""
+    counts = largest_remainder(total, weights)
+    keys: List[RSAKey] = []
+    kinds, kids, inputs = [], [], []
+    for si, (bits, cnt) in enumerate(zip(sizes, counts)):
+        ks = make_keys(bits, seed, keys_per_size)
+        first = len(keys)
+        keys.extend(ks)
+        L = ks[0].limbs
+        k_of = np.arange(cnt) % keys_per_size
+        vals = np.zeros((cnt, L), dtype=np.uint32)
+        for j, key in enumerate(ks):
+            idx = np.nonzero(k_of == j)[0]
+            if idx.size:
+                vals[idx] = uniform_below(key.n, idx.size, derive_seed(seed, bits, j, 3), L)
+        kinds.append(np.arange(cnt) % 2)
+        kids.append(first + k_of)
+        inputs.extend(vals)
+    kinds_a = np.concatenate(kinds).astype(np.int64)
+    kids_a = np.concatenate(kids).astype(np.int64)
+    perm = np.argsort(splitmix64_block(derive_seed(seed, 77), 0, len(kinds_a)), kind="stable")
+    kinds_a, kids_a = kinds_a[perm], kids_a[perm]
+    inputs = [inputs[i] for i in perm.tolist()]
+    lens = np.array([len(v) for v in inputs], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(lens)[:-1]]).astype(np.int64)
+    pool = np.concatenate(inputs).astype(np.uint32) if inputs else np.zeros(0, np.uint32)
+    return MixedWorkload(name, keys, kinds_a, kids_a, offs, pool, int(lens.sum()))
+
+
+def workload_c4(total: int = 32768, keys_per_size: int = 16) -> MixedWorkload:
+    """1024/2048/3072/4096-bit keys in ratio 4:8:2:1, half encryptions
+    (e = 65537), half CRT decryptions, 16 keys per size."""
+    return mixed_workload("rsa-mixed-1k-4k", [1024, 2048, 3072, 4096], [4, 8, 2, 1], total,
+                          keys_per_size, SEED_BASE + 4)
