@@ -100,6 +100,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512,
                     help="messages the CPU oracle processes for the baseline (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a known-size reference "
+                         "dispatch for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -114,6 +117,12 @@ def main():
     from paper_1407_1465_amd import rsagpu
     from paper_1407_1465_amd import workloads as W
     torch.cuda.set_device(0)
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def dev(a):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()

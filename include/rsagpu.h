@@ -122,6 +122,18 @@ int rsa_get_plan(int limbs, int kind, rsa_plan *plan);
 int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int window_bits);
 
 /*
+ * Autotuner: for the width class of `limbs` (kind 0: exponentiation of
+ * `limbs`-word operands with exp_bits-bit exponents; kind 1: CRT decryption
+ * of `limbs`-word moduli with exp_bits-bit dp, dq; exp_bits <= 0 means full
+ * length), times every compiled kernel instance of the class at every window
+ * width that fits, on `count` synthetic operands, and installs the fastest
+ * plan (rsa_set_plan).  Allocates and frees its own device buffers and
+ * synchronises `stream`; not for use inside a timed or captured region.
+ * The chosen plan is written to *best when not NULL.
+ */
+int rsa_autotune(int limbs, int kind, int exp_bits, size_t count, hipStream_t stream, rsa_plan *best);
+
+/*
  * Sets up the current device's library state (the data-error counter, one
  * 8-byte device allocation made once per device).  Every other entry point
  * does this on first use; call it explicitly before capturing any library

@@ -46,6 +46,8 @@ _lib.rsa_get_plan.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_Plan)]
 _lib.rsa_get_plan.restype = ctypes.c_int
 _lib.rsa_set_plan.argtypes = [ctypes.c_int] * 5
 _lib.rsa_set_plan.restype = ctypes.c_int
+_lib.rsa_autotune.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_size_t, _P, ctypes.POINTER(_Plan)]
+_lib.rsa_autotune.restype = ctypes.c_int
 _lib.rsa_init.argtypes = []
 _lib.rsa_init.restype = ctypes.c_int
 
@@ -63,7 +65,7 @@ _lib.rsa_ops_batch.argtypes = [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P,
 _lib.rsa_ops_batch.restype = ctypes.c_int
 
 # exported symbols, in the order include/rsagpu.h declares them
-EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_get_plan", "rsa_set_plan", "rsa_init",
+EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_get_plan", "rsa_set_plan", "rsa_autotune", "rsa_init",
            "rsa_keyset_create", "rsa_keyset_add", "rsa_keyset_destroy", "rsa_ops_workspace_size",
            "rsa_ops_batch", "rsa_device_errors", "rsa_status_str", "rsa_version")
 
@@ -101,6 +103,14 @@ def get_plan(limbs: int, kind: int = 0) -> Plan:
 def set_plan(limbs: int, kind: int, radix_bits: int, lanes_per_op: int, window_bits: int) -> None:
     """Override the plan of a limb width (all zero restores the default)."""
     _check(_lib.rsa_set_plan(limbs, kind, radix_bits, lanes_per_op, window_bits), "rsa_set_plan")
+
+
+def autotune(limbs: int, kind: int, exp_bits: int, count: int,
+             stream: Optional[torch.cuda.Stream] = None) -> Plan:
+    """Times every kernel instance / window for the class and installs the fastest."""
+    p = _Plan()
+    _check(_lib.rsa_autotune(limbs, kind, exp_bits, count, _stream_handle(stream), ctypes.byref(p)), "rsa_autotune")
+    return Plan(p.radix_bits, p.padded_limbs, p.lanes_per_op, p.limbs_per_lane, p.window_bits, p.lds_bytes)
 
 
 def init() -> None:

@@ -1,0 +1,84 @@
+"""Autotuned plans, cached on disk per device architecture.
+
+`tune(limbs, kind, exp_bits, count)` runs the library's autotuner
+(rsa_autotune: every compiled kernel instance of the width class at every
+window that fits, timed on synthetic operands of the given batch size) and
+records the winner in a JSON cache; `apply_cached()` re-installs cached plans
+with rsa_set_plan so later processes skip the search.  Entries are keyed by
+the GPU architecture, the operand width class, the kind, the exponent length
+and the batch size rounded to a power of two.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Optional
+
+import torch
+
+from . import rsagpu
+
+_DEFAULT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), ".tunecache",
+                        "plans.json")
+
+
+def cache_path() -> str:
+    return os.environ.get("RSAGPU_TUNE_FILE", _DEFAULT)
+
+
+def _arch() -> str:
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _key(limbs: int, kind: int, exp_bits: int, count: int) -> str:
+    cls = rsagpu.get_plan(limbs if kind == 0 else limbs // 2, kind).padded_limbs
+    bucket = 1 << max(0, (count - 1).bit_length())
+    return "%s/w%d/k%d/e%d/n%d" % (_arch(), limbs, kind, exp_bits, bucket)
+
+
+def load() -> Dict[str, dict]:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save(cache: Dict[str, dict]) -> None:
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(limbs: int, kind: int, exp_bits: int, count: int, use_cache: bool = True) -> rsagpu.Plan:
+    """Best plan for (limbs, kind, exp_bits, count), installed in the library."""
+    cache = load()
+    key = _key(limbs, kind, exp_bits, count)
+    width = limbs if kind == 0 else limbs // 2
+    if use_cache and key in cache:
+        e = cache[key]
+        rsagpu.set_plan(width, kind, e["radix_bits"], e["lanes_per_op"], e["window_bits"])
+        return rsagpu.get_plan(width, kind)
+    plan = rsagpu.autotune(limbs, kind, exp_bits, count)
+    cache[key] = {"radix_bits": plan.radix_bits, "lanes_per_op": plan.lanes_per_op,
+                  "window_bits": plan.window_bits, "padded_limbs": plan.padded_limbs}
+    save(cache)
+    return plan
+
+
+def apply_cached(arch: Optional[str] = None) -> int:
+    """Installs every cached plan of this architecture; returns how many."""
+    arch = arch or _arch()
+    n = 0
+    for key, e in load().items():
+        parts = key.split("/")
+        if parts[0] != arch:
+            continue
+        limbs, kind = int(parts[1][1:]), int(parts[2][1:])
+        width = limbs if kind == 0 else limbs // 2
+        rsagpu.set_plan(width, kind, e["radix_bits"], e["lanes_per_op"], e["window_bits"])
+        n += 1
+    return n

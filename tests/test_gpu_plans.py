@@ -100,3 +100,25 @@ def test_instance_crt(B, S, G, plan_guard):
     bad = np.nonzero((out != want).any(axis=1))[0]
     assert bad.size == 0, "B=%d S=%d G=%d: %d bad" % (B, S, G, bad.size)
     assert rsagpu.device_errors() == 0
+
+
+def test_autotune_installs_a_working_plan(plan_guard):
+    plan_guard.append((32, 1))
+    plan_guard.append((16, 0))
+    best = rsagpu.autotune(64, 1, 0, 1024)
+    assert rsagpu.get_plan(32, 1) == best
+    best0 = rsagpu.autotune(16, 0, 17, 2048)
+    assert rsagpu.get_plan(16, 0) == best0
+    keys = W.make_keys(2048, 4242 + 2048, 2)
+    L, h = keys[0].limbs, keys[0].limbs // 2
+    key_of = np.arange(10) % 2
+    rng = random.Random(5)
+    C = W.ints_to_limbs([rng.randrange(keys[k].n) for k in key_of], L)
+
+    def col(attr, width):
+        return np.ascontiguousarray(W.ints_to_limbs([getattr(k, attr) for k in keys], width)[key_of])
+
+    out = host(rsagpu.decrypt_crt(dev(C), dev(col("p", h)), dev(col("q", h)), dev(col("dp", h)),
+                                  dev(col("dq", h)), dev(col("qinv", h))))
+    assert np.array_equal(out, oracle_modexp(C, col("d", L), col("n", L)))
+    assert rsagpu.device_errors() == 0
