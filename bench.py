@@ -72,10 +72,39 @@ def timed(fn, steps, warmup, torch):
     return ev0.elapsed_time(ev1) / steps, time.perf_counter() - wall0
 
 
+def kernel_src_hash():
+    """sha256 over the library's kernel and host sources (csrc)."""
+    import glob
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1407_1465_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip")) +
+                    glob.glob(os.path.join(csrc, "*.def"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter profile of `kernel`
+    (FETCH_SIZE and WRITE_SIZE runs scaled by a plain copy of known size), or
+    None when there is none or the sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "k_crt_rsa2048_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel.replace(" ", "") or t.get("src_sha256") != kernel_src_hash():
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
 def roofline(products, ms, kernel):
     achieved = products / (ms / 1e3)
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_MUL_PEAK / 1e12,
-            "unit": "T int32-mul/s", "frac": achieved / INT32_MUL_PEAK, "traffic": None,
+            "unit": "T int32-mul/s", "frac": achieved / INT32_MUL_PEAK, "traffic": measured_traffic(kernel),
             "kernel": kernel, "products_per_launch": products}
 
 
@@ -155,6 +184,19 @@ def main():
             if not torch.equal(back, c[idx]):
                 raise SystemExit("round-trip check failed")
             products = sum(crt_products(wl.keys[k], plan.window_bits) for k in wl.key_of.tolist())
+            # the same batch as one launch per key (plain form, no cross-key batching)
+            per_key = []
+            for j in range(len(wl.keys)):
+                idx_j = torch.from_numpy(np.nonzero(wl.key_of == j)[0]).cuda()
+                per_key.append([t[idx_j].contiguous() for t in (c, p, q, dp, dq, qi)] + [None])
+                per_key[-1][-1] = torch.empty_like(per_key[-1][0])
+
+            def plain():
+                for a in per_key:
+                    rsagpu.decrypt_crt(*a[:6], out=a[6])
+            ms_plain, _ = timed(plain, max(1, args.steps // 4), 1, torch)
+            line["plain_one_key_per_launch"] = {"value": count / (ms_plain / 1e3), "ms_per_step": ms_plain,
+                                                "launches": len(per_key)}
             line.update(metric=METRIC, unit="decryptions/s",
                         config={"workload": "rsa2048-crt-decrypt", "keys": len(wl.keys), "messages": count,
                                 "modulus_bits": 32 * L, "radix_bits": plan.radix_bits,
