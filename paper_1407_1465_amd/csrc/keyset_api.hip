@@ -75,6 +75,13 @@ struct rsa_keyset {
     rsagpu::KeyHostInfo *info;      // host copy per key
     unsigned class_mask;            // width classes present
     std::mutex mu;
+    // fork/join of the per-bucket kernels (created on first use)
+    static const int kStreams = 8;
+    hipStream_t streams[kStreams];
+    hipEvent_t fork;
+    hipEvent_t done[2 * 16];
+    bool have_streams;
+    std::mutex launch_mu;
 };
 
 namespace rsagpu {
@@ -163,6 +170,11 @@ extern "C" int rsa_keyset_destroy(rsa_keyset *ks)
     if (ks->stage_mods) (void)hipFree(ks->stage_mods);
     if (ks->stage_words) (void)hipFree(ks->stage_words);
     if (ks->stage_outs) (void)hipFree(ks->stage_outs);
+    if (ks->have_streams) {
+        for (hipStream_t s : ks->streams) (void)hipStreamDestroy(s);
+        (void)hipEventDestroy(ks->fork);
+        for (hipEvent_t e : ks->done) (void)hipEventDestroy(e);
+    }
     delete[] ks->info;
     delete ks;
     return RSA_OK;
@@ -281,6 +293,21 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
     int cus = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 1;
+
+    // The buckets run concurrently: each on one of the keyset's streams,
+    // forked from `stream` after the bucketing and joined back into it, so
+    // small or latency-bound buckets overlap the large ones.
+    std::lock_guard<std::mutex> launch_lock(ks->launch_mu);
+    if (!ks->have_streams) {
+        for (hipStream_t &st : ks->streams)
+            if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return status_of(e);
+        if ((e = hipEventCreateWithFlags(&ks->fork, hipEventDisableTiming)) != hipSuccess) return status_of(e);
+        for (hipEvent_t &ev : ks->done)
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return status_of(e);
+        ks->have_streams = true;
+    }
+    if ((e = hipEventRecord(ks->fork, stream)) != hipSuccess) return status_of(e);
+    int used = 0;
     // most expensive buckets first: wide classes, decryptions before encryptions
     for (int cls = num_classes() - 1; cls >= 0; --cls) {
         if (!(mask & (1u << cls))) continue;
@@ -292,10 +319,16 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
             int per = r.inst->blocks_per_cu(kind, r.w);
             if (per <= 0) per = 1;
             const int blocks = per * cus;
+            hipStream_t s = ks->streams[used % rsa_keyset::kStreams];
+            if ((e = hipStreamWaitEvent(s, ks->fork, 0)) != hipSuccess) return status_of(e);
             const ops_launcher fn = kind == 0 ? r.inst->ops_enc : r.inst->ops_crt;
             e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b,
-                   counters + b, in_pool, out_pool, r.w, blocks, stream);
+                   counters + b, in_pool, out_pool, r.w, blocks, s);
             if (e != hipSuccess) return status_of(e);
+            hipEvent_t done = ks->done[used % (2 * 16)];
+            if ((e = hipEventRecord(done, s)) != hipSuccess) return status_of(e);
+            if ((e = hipStreamWaitEvent(stream, done, 0)) != hipSuccess) return status_of(e);
+            ++used;
         }
     }
     return RSA_OK;
