@@ -162,7 +162,7 @@ typedef struct {
 } rsa_op;
 
 /* Creates an empty keyset for up to max_keys keys on the current device.
- * Allocates the keyset's device memory once (~6.7 KB per key). */
+ * Allocates the keyset's device memory once (~8.3 KB per key). */
 int rsa_keyset_create(rsa_keyset **ks, int max_keys);
 
 /*

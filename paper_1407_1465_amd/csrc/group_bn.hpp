@@ -64,11 +64,21 @@ __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
 }
 
+// Every lane written; a lane whose source is outside its row reads 0
+// (bound_ctrl).  No previous value is involved, so the destination needs no
+// initialising move.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, true);
+}
+
 enum : int {
     DPP_QP_0000 = 0x00,      // quad_perm [0,0,0,0]
     DPP_QP_0022 = 0xA0,      // quad_perm [0,0,2,2]
     DPP_QP_1230 = 0x39,      // quad_perm [1,2,3,0]
     DPP_QP_1032 = 0xB1,      // quad_perm [1,0,3,2]
+    DPP_QP_1133 = 0xF5,      // quad_perm [1,1,3,3]
     DPP_ROW_SHL1 = 0x101,    // lane i <- lane i+1 within a row of 16
     DPP_ROW_SHR1 = 0x111,    // lane i <- lane i-1 within a row of 16
     DPP_ROW_SHR4 = 0x114,
@@ -80,13 +90,13 @@ template <int G>
 __device__ __forceinline__ uint32_t grp_bcast0(uint32_t v)
 {
     if constexpr (G == 1) return v;
-    else if constexpr (G == 2) return dpp<DPP_QP_0022>(0, v);
-    else if constexpr (G == 4) return dpp<DPP_QP_0000>(0, v);
+    else if constexpr (G == 2) return dpp0<DPP_QP_0022>(v);
+    else if constexpr (G == 4) return dpp0<DPP_QP_0000>(v);
     else if constexpr (G == 8) {
-        const uint32_t q = dpp<DPP_QP_0000>(0, v);
+        const uint32_t q = dpp0<DPP_QP_0000>(v);
         return dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);           // banks 1, 3 take banks 0, 2
     } else if constexpr (G == 16) {
-        uint32_t q = dpp<DPP_QP_0000>(0, v);
+        uint32_t q = dpp0<DPP_QP_0000>(v);
         q = dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);
         return dpp<DPP_ROW_SHR8, 0xF, 0xC>(q, q);           // banks 2, 3 take banks 0, 1
     } else return (uint32_t)__shfl((int)v, 0, G);
@@ -107,12 +117,12 @@ template <int G>
 __device__ __forceinline__ uint32_t grp_rot_down(uint32_t v)
 {
     if constexpr (G == 1) return 0;
-    else if constexpr (G == 2) return dpp<DPP_QP_1032>(0, v);
-    else if constexpr (G == 4) return dpp<DPP_QP_1230>(0, v);
+    else if constexpr (G == 2) return dpp0<DPP_QP_1032>(v);
+    else if constexpr (G == 4) return dpp0<DPP_QP_1230>(v);
     else if constexpr (G == 8) {
-        const uint32_t u = dpp<DPP_ROW_SHL1>(0, v);
+        const uint32_t u = dpp0<DPP_ROW_SHL1>(v);
         return (lane_id() & 7) == 7 ? 0u : u;
-    } else if constexpr (G == 16) return dpp<DPP_ROW_SHL1>(0, v);
+    } else if constexpr (G == 16) return dpp0<DPP_ROW_SHL1>(v);
     else {
         const uint32_t u = (uint32_t)__shfl_down((int)v, 1, G);
         return (lane_id() & (G - 1)) == G - 1 ? 0u : u;
@@ -125,7 +135,7 @@ __device__ __forceinline__ uint32_t grp_from_above(uint32_t v)
 {
     if constexpr (G == 1) return 0;
     else {
-        const uint32_t u = (G <= 16) ? dpp<DPP_ROW_SHL1>(0u, v)
+        const uint32_t u = (G <= 16) ? dpp0<DPP_ROW_SHL1>(v)
                                      : (uint32_t)__shfl_down((int)v, 1, G);
         return (lane_id() & (G - 1)) == G - 1 ? 0u : u;
     }
@@ -137,7 +147,7 @@ __device__ __forceinline__ uint32_t grp_from_below(uint32_t v)
 {
     if constexpr (G == 1) return 0;
     else {
-        const uint32_t u = (G <= 16) ? dpp<DPP_ROW_SHR1>(0, v)
+        const uint32_t u = (G <= 16) ? dpp0<DPP_ROW_SHR1>(v)
                                      : (uint32_t)__shfl_up((int)v, 1, G);
         return (lane_id() & (G - 1)) == 0 ? 0u : u;
     }

@@ -93,7 +93,8 @@ static size_t key_words_for(int cls, int hcls)
 {
     const size_t W = (size_t)class_width(cls), H = (size_t)class_width(hcls);
     size_t w = 2 * W + 5 * H;                                         // n, e, p, q, dp, dq, qinv
-    for (int B : {32, 29}) w += 2 * s_for(cls, B) + 4 * s_for(hcls, B);  // one, r2 of n, p, q
+    // one, r2 of n; one, r2, r3 of p and q; qinv * R of p
+    for (int B : {32, 29}) w += 2 * s_for(cls, B) + 7 * s_for(hcls, B);
     return w;
 }
 
@@ -215,9 +216,11 @@ extern "C" int rsa_keyset_add(rsa_keyset *ks, int limbs, const uint32_t *n, cons
     for (int slot = 0; slot < 2; ++slot) {
         const int B = slot == 0 ? 32 : 29;
         const size_t sn = s_for(cls, B), sh = s_for(hcls, B);
-        kd.cn[slot] = ModConsts{sn ? take(sn) : nullptr, sn ? take(sn) : nullptr};
-        kd.cp[slot] = ModConsts{sh ? take(sh) : nullptr, sh ? take(sh) : nullptr};
-        kd.cq[slot] = ModConsts{sh ? take(sh) : nullptr, sh ? take(sh) : nullptr};
+        kd.cn[slot] = ModConsts{sn ? take(sn) : nullptr, sn ? take(sn) : nullptr, nullptr, nullptr};
+        kd.cp[slot] = ModConsts{sh ? take(sh) : nullptr, sh ? take(sh) : nullptr, sh ? take(sh) : nullptr,
+                                sh ? take(sh) : nullptr};
+        kd.cq[slot] = ModConsts{sh ? take(sh) : nullptr, sh ? take(sh) : nullptr, sh ? take(sh) : nullptr,
+                                nullptr};
     }
     if ((size_t)(cur - base) > ks->key_words) return RSA_ELIMBS;
 
@@ -232,17 +235,19 @@ extern "C" int rsa_keyset_add(rsa_keyset *ks, int limbs, const uint32_t *n, cons
     // Montgomery constants of n (class cls) and p, q (class hcls), each radix
     for (int slot = 0; slot < 2; ++slot) {
         const int B = slot == 0 ? 32 : 29;
-        struct Job { int c; const uint32_t *m; int words; ModConsts out; };
-        Job jobs[3] = {{cls, dn, limbs, kd.cn[slot]}, {hcls, dpp, h, kd.cp[slot]}, {hcls, dqq, h, kd.cq[slot]}};
+        struct Job { int c; const uint32_t *m; const uint32_t *x; int words; ModConsts out; };
+        Job jobs[3] = {{cls, dn, nullptr, limbs, kd.cn[slot]}, {hcls, dpp, dqi, h, kd.cp[slot]},
+                       {hcls, dqq, nullptr, h, kd.cq[slot]}};
         for (const Job &j : jobs) {
             if (!j.out.one) continue;
             const Instance *in = any_instance(j.c, B);
             if (!in) continue;
-            const uint32_t *mp = j.m;
-            err = hipMemcpy(ks->stage_mods, &mp, sizeof(mp), hipMemcpyHostToDevice);
+            const uint32_t *mp[2] = {j.m, j.x};                     // modulus, multiplier
+            err = hipMemcpy(ks->stage_mods, mp, sizeof(mp), hipMemcpyHostToDevice);
             if (err == hipSuccess) err = hipMemcpy(ks->stage_words, &j.words, sizeof(int), hipMemcpyHostToDevice);
             if (err == hipSuccess) err = hipMemcpy(ks->stage_outs, &j.out, sizeof(ModConsts), hipMemcpyHostToDevice);
-            if (err == hipSuccess) err = in->setup(ks->stage_mods, ks->stage_words, ks->stage_outs, 1, nullptr);
+            if (err == hipSuccess)
+                err = in->setup(ks->stage_mods, ks->stage_mods + 1, ks->stage_words, ks->stage_outs, 1, nullptr);
             if (err == hipSuccess) err = hipStreamSynchronize(nullptr);
             if (err != hipSuccess) return status_of(err);
         }

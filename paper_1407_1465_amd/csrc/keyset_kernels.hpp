@@ -3,9 +3,11 @@
 //
 // A key is held on the device as its raw 32-bit-word material (n, e, p, q,
 // dp, dq, qinv) plus, for each limb radix the library computes in, the
-// Montgomery constants one = R mod m and r2 = R^2 mod m of m = n, p and q,
-// stored as the kernel's limbs.  They are computed once when the key is added,
-// so an operation starts directly with its exponentiation.
+// Montgomery constants of m = n, p and q stored as the kernel's limbs:
+// one = R mod m and r2 = R^2 mod m for all three, r3 = R^3 mod m for p and q
+// (CRT entry of a full-width ciphertext), and qinv * R mod p (Garner's
+// multiplier in Montgomery form).  They are computed once when the key is
+// added, so an operation starts directly with its exponentiation.
 //
 // Operations are grouped on the device into buckets of one (width class,
 // kind); each bucket is served by a persistent kernel whose waves claim
@@ -16,10 +18,14 @@
 
 namespace rsagpu {
 
-// Constants of one modulus in one radix: `one` and `r2`, S limbs each.
+// Constants of one modulus m in one radix, S limbs each: one = R mod m,
+// r2 = R^2 mod m, r3 = R^3 mod m and xr = x * R mod m for a multiplier x given
+// at setup.  r3 and xr are null where no kernel needs them.
 struct ModConsts {
     uint32_t *one;
     uint32_t *r2;
+    uint32_t *r3;
+    uint32_t *xr;
 };
 
 // Device view of one resident key.
@@ -62,11 +68,13 @@ __device__ __forceinline__ void store_raw(uint32_t *p, const uint32_t (&x)[S / G
     for (int k = 0; k < L; ++k) p[r * L + k] = x[k];
 }
 
-// Constants of `count` moduli (32-bit words each at mods[i]): one, r2 in
-// radix 2^B with S limbs, written to outs[i] (the caller validated the moduli).
+// Constants of `count` moduli (32-bit words each at mods[i]) in radix 2^B
+// with S limbs, written to outs[i]; xr from the multiplier mults[i] (same word
+// count, below the modulus) where outs[i].xr is set.  The caller validated
+// the moduli.
 template <int S, int G, int B>
-__global__ __launch_bounds__(64) void k_setup(const uint32_t *const *mods, const int *words, ModConsts *outs,
-                                              int count)
+__global__ __launch_bounds__(64) void k_setup(const uint32_t *const *mods, const uint32_t *const *mults,
+                                              const int *words, ModConsts *outs, int count)
 {
     using Ar = Arith<S, G, B>;
     using Ly = Layout<S, G>;
@@ -81,12 +89,18 @@ __global__ __launch_bounds__(64) void k_setup(const uint32_t *const *mods, const
     const uint32_t bl = Ar::bitlen(n);
     const bool valid = live && (n0 & 1u) && bl > 1;
     const uint32_t n0inv = Ar::n0inv(n0 | 1u);
-    uint32_t one[L], r2[L];
+    uint32_t one[L], r2[L], t[L];
     mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds, lds + Ly::WORDS);
-    if (live) {
-        store_raw<S, G>(outs[i].one, one, true);
-        store_raw<S, G>(outs[i].r2, r2, true);
-    }
+    const ModConsts oc = live ? outs[i] : ModConsts{nullptr, nullptr, nullptr, nullptr};
+    store_raw<S, G>(oc.one, one, live);
+    store_raw<S, G>(oc.r2, r2, live);
+    mont_mul_reg<S, G, B>(t, r2, r2, lds, n, n0inv);           // R^3 mod m
+    store_raw<S, G>(oc.r3, t, live && oc.r3);
+    const bool want_x = live && oc.xr && mults[i];
+    uint32_t x[L];
+    Ar::load(x, want_x ? mults[i] : nullptr, want_x ? words[i] : 0, 0, want_x);
+    mont_mul_reg<S, G, B>(t, x, r2, lds, n, n0inv);            // x * R mod m
+    store_raw<S, G>(oc.xr, t, want_x);
 }
 
 // Claims the next chunk of `n` operations of a bucket for this wave.
@@ -100,7 +114,7 @@ __device__ __forceinline__ unsigned claim(unsigned *counter, unsigned n)
 // Bucket of encryptions (in^e mod n) for keys of one width class: S limbs of
 // radix 2^B hold n.
 template <int S, int G, int B>
-__global__ __launch_bounds__(64) void k_ops_enc(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
+__global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
                                                 const unsigned *__restrict__ list, const unsigned *count_p,
                                                 unsigned *counter, const uint32_t *__restrict__ in_pool,
                                                 uint32_t *out_pool, int w)
@@ -156,23 +170,23 @@ __global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys,
         const KeyDev &k = keys[op.key_id];
         const int hl = k.hwords, full = 2 * hl;
         const ModConsts &mc = half ? k.cq[radix_slot<B>()] : k.cp[radix_slot<B>()];
-        uint32_t n[L], other[L], clo[L], chi[L], one[L], r2[L], r3[L];
+        uint32_t n[L], clo[L], chi[L], one[L], rk[L];
         Ar::load(n, half ? k.q : k.p, hl, 0, live);
-        Ar::load(other, half ? k.p : k.q, hl, 0, live);
         Ar::load(clo, in_pool + op.in_off, full, 0, live);
         Ar::load(chi, in_pool + op.in_off, full, B * H, live);
-        load_raw<H, G>(one, mc.one, live);
-        load_raw<H, G>(r2, mc.r2, live);
         const uint32_t n0inv = Ar::n0inv(grp_bcast0<G>(n[0]) | 1u);
-        mont_mul_reg<H, G, B>(r3, r2, r2, lds, n, n0inv);
+        // xt = c * R mod m = c_lo * R^2 * R^-1 + c_hi * R^3 * R^-1  (c = c_lo + c_hi * R)
         uint32_t xt[L], t2[L];
-        mont_mul_reg<H, G, B>(xt, clo, r2, lds, n, n0inv);
-        mont_mul_reg<H, G, B>(t2, chi, r3, lds, n, n0inv);
+        load_raw<H, G>(rk, mc.r2, live);
+        mont_mul_reg<H, G, B>(xt, clo, rk, lds, n, n0inv);
+        load_raw<H, G>(rk, mc.r3, live);
+        mont_mul_reg<H, G, B>(t2, chi, rk, lds, n, n0inv);
         {
             const uint32_t ovf = Ar::add(xt, t2);
             Ar::cond_sub(xt, ovf, n);
         }
         uint32_t A[L];
+        load_raw<H, G>(one, mc.one, live);
         group_modexp<H, G, B>(A, xt, half ? k.dq : k.dp, hl, live, n, n0inv, one, lds, w);
         from_mont<H, G, B>(A, lds, n, n0inv);
 
@@ -190,8 +204,7 @@ __global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys,
 #pragma unroll
             for (int j = 0; j < L; ++j) A[j] = neg ? e[j] : d[j];
         }
-        Ar::load(qv, k.qinv, hl, 0, live && !half);
-        mont_mul_reg<H, G, B>(qv, qv, r2, lds, n, n0inv);
+        load_raw<H, G>(qv, k.cp[radix_slot<B>()].xr, live && !half);     // qinv * R mod p
         mont_mul_reg<H, G, B>(hh, A, qv, lds, n, n0inv);
         lds_sync();
         lds_put<H, G>(lds, hh);
@@ -200,7 +213,8 @@ __global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys,
         auto sink = [&](int i, uint32_t v) {
             if (r == 0) stage[i] = v;
         };
-        uint32_t high[L];
+        uint32_t high[L], other[L];
+        Ar::load(other, k.q, hl, 0, live);
         Ar::mul_wide(high, mq, other, lds, sink);
 #pragma unroll
         for (int j = 0; j < L; ++j) stage[H + r * L + j] = high[j];

@@ -20,8 +20,8 @@ struct KeyDev;
 struct ModConsts;
 struct OpDesc;
 
-typedef hipError_t (*setup_launcher)(const uint32_t *const *mods, const int *words, ModConsts *outs, int count,
-                                     hipStream_t stream);
+typedef hipError_t (*setup_launcher)(const uint32_t *const *mods, const uint32_t *const *mults, const int *words,
+                                     ModConsts *outs, int count, hipStream_t stream);
 // Persistent bucket kernel: `blocks` workgroups claim operations until the
 // bucket (list, *count) is exhausted.
 typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const unsigned *list,
@@ -43,8 +43,8 @@ hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, c
                       unsigned long long *errs, hipStream_t stream);
 
 template <int S, int G, int B>
-hipError_t launch_setup(const uint32_t *const *mods, const int *words, ModConsts *outs, int count,
-                        hipStream_t stream);
+hipError_t launch_setup(const uint32_t *const *mods, const uint32_t *const *mults, const int *words,
+                        ModConsts *outs, int count, hipStream_t stream);
 
 template <int S, int G, int B>
 hipError_t launch_ops_enc(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,

@@ -30,13 +30,13 @@ hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, c
 }
 
 template <int S, int G, int B>
-hipError_t launch_setup(const uint32_t *const *mods, const int *words, ModConsts *outs, int count,
-                        hipStream_t stream)
+hipError_t launch_setup(const uint32_t *const *mods, const uint32_t *const *mults, const int *words,
+                        ModConsts *outs, int count, hipStream_t stream)
 {
     const int ng = 64 / G;
     const int blocks = (count + ng - 1) / ng;
-    hipLaunchKernelGGL((k_setup<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, 2), stream, mods, words,
-                       outs, count);
+    hipLaunchKernelGGL((k_setup<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, 2), stream, mods, mults,
+                       words, outs, count);
     return hipGetLastError();
 }
 
@@ -81,8 +81,9 @@ int ops_blocks_per_cu(int kind, int w)
                                                    const uint32_t *, const uint32_t *, const uint32_t *,    \
                                                    uint32_t *, size_t, int, int, unsigned long long *,      \
                                                    hipStream_t);                                            \
-    template hipError_t rsagpu::launch_setup<S_, G_, B_>(const uint32_t *const *, const int *,              \
-                                                         rsagpu::ModConsts *, int, hipStream_t);            \
+    template hipError_t rsagpu::launch_setup<S_, G_, B_>(const uint32_t *const *, const uint32_t *const *,  \
+                                                         const int *, rsagpu::ModConsts *, int,             \
+                                                         hipStream_t);                                      \
     template hipError_t rsagpu::launch_ops_enc<S_, G_, B_>(                                                 \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
         const uint32_t *, uint32_t *, int, int, hipStream_t);                                               \

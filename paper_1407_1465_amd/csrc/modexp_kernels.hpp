@@ -14,6 +14,17 @@
 #include "group_bn.hpp"
 #include "radix_bn.hpp"
 
+// Minimum waves per SIMD a plain exponentiation kernel is compiled for (the
+// register budget per lane is 512 / waves).  With 14 or more limbs per lane
+// the unconstrained allocation exceeds 256 registers, one wave per SIMD;
+// capping it at two waves costs a few spills outside the product loop and
+// hides the loop's dependency chains behind a second wave.  The CRT kernels
+// are left unconstrained: at their best windows the LDS table already limits
+// them to one wave per SIMD.
+template <int L>
+constexpr int exp_waves_per_simd() { return L >= 14 ? 2 : 1; }
+#define RSAGPU_EXP_OCC(L) __attribute__((amdgpu_waves_per_eu(exp_waves_per_simd<(L)>())))
+
 namespace rsagpu {
 
 extern __shared__ uint4 rsagpu_lds[];
@@ -32,6 +43,12 @@ struct Arith {
                                                     const uint32_t (&n)[L], uint32_t n0inv)
     {
         rmont_mul<S, G, B>(r, a, b, n, n0inv);
+    }
+    // Result below 2n with redundant limbs (see rmont_mul); inputs likewise.
+    static __device__ __forceinline__ void mont_mul_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                         const uint32_t *b, const uint32_t (&n)[L], uint32_t n0inv)
+    {
+        rmont_mul<S, G, B, true>(r, a, b, n, n0inv);
     }
     template <typename Sink>
     static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
@@ -74,6 +91,12 @@ struct Arith<S, G, 32> {
     }
     static __device__ __forceinline__ void mont_mul(uint32_t (&r)[L], const uint32_t (&a)[L], const uint32_t *b,
                                                     const uint32_t (&n)[L], uint32_t n0inv)
+    {
+        rsagpu::mont_mul<S, G>(r, a, b, n, n0inv);
+    }
+    // Radix 2^32 limbs are exact fits (2n may not fit S limbs): canonical.
+    static __device__ __forceinline__ void mont_mul_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                         const uint32_t *b, const uint32_t (&n)[L], uint32_t n0inv)
     {
         rsagpu::mont_mul<S, G>(r, a, b, n, n0inv);
     }
@@ -146,6 +169,23 @@ __device__ __forceinline__ void mont_sqr(uint32_t (&A)[S / G], uint32_t *abuf, c
     mont_mul_reg<S, G, B>(A, A, A, abuf, n, n0inv);
 }
 
+// Lazy form of mont_sqr (result below 2n, limbs possibly redundant).  In
+// radix 2^29 with 2 or 4 lanes per group the multiplier comes straight from
+// the group's registers (DPP quad permutes), skipping the LDS round trip.
+template <int S, int G, int B>
+__device__ __forceinline__ void mont_sqr_lazy(uint32_t (&A)[S / G], uint32_t *abuf, const uint32_t (&n)[S / G],
+                                              uint32_t n0inv)
+{
+    if constexpr (B != 32 && (G == 2 || G == 4)) {
+        rmont_sqr_reg<S, G, B, true>(A, A, n, n0inv);
+    } else {
+        lds_sync();
+        lds_put<S, G>(abuf, A);
+        lds_sync();
+        Arith<S, G, B>::mont_mul_lazy(A, A, abuf, n, n0inv);
+    }
+}
+
 // Montgomery constants of an odd modulus n > 1 in radix 2^B, R = 2^(B*S):
 //   one = R mod n:   2^(bitlen(n)-1) doubled B*S - bitlen(n) + 1 times;
 //   r2 = R^2 mod n:  X = 2R mod n, then left-to-right over the bits of B*S
@@ -216,7 +256,8 @@ __device__ __forceinline__ uint32_t exp_digit(const uint32_t *ep, int elimbs, in
 // digit initialises A directly (the w squarings of 1 are skipped); a zero
 // digit skips its product.  The window count is the wave's largest exponent
 // length, so groups with shorter exponents run on A = 1 until their digits
-// start.
+// start.  Every product here is lazy: A and the table stay below 2n in
+// redundant limbs, and the caller's from_mont makes the result canonical.
 template <int S, int G, int B>
 __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
                                              const uint32_t *ep, int elimbs, bool use_exp,
@@ -239,7 +280,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     lds_sync();
     const int tsize = 1 << w;
     for (int i = 2; i < tsize; ++i) {
-        Ar::mont_mul(cur, cur, tbl, n, n0inv);
+        Ar::mont_mul_lazy(cur, cur, tbl, n, n0inv);
         lds_put<S, G>(tbl + (i - 1) * Ly::WORDS, cur);
     }
     lds_sync();
@@ -272,10 +313,10 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     }
     for (int win = nwin - 2; win >= 0; --win) {
         d = use_exp ? exp_digit(ep, elimbs, win * w, w) : 0u;
-        for (int s = 0; s < w; ++s) mont_sqr<S, G, B>(A, abuf, n, n0inv);
+        for (int s = 0; s < w; ++s) mont_sqr_lazy<S, G, B>(A, abuf, n, n0inv);
         if (__ballot(d != 0u)) {
             uint32_t t[L];
-            Ar::mont_mul(t, A, tbl + ((d ? d : 1u) - 1) * Ly::WORDS, n, n0inv);
+            Ar::mont_mul_lazy(t, A, tbl + ((d ? d : 1u) - 1) * Ly::WORDS, n, n0inv);
 #pragma unroll
             for (int k = 0; k < L; ++k) A[k] = d ? t[k] : A[k];
         }
@@ -298,7 +339,7 @@ __device__ __forceinline__ void from_mont(uint32_t (&A)[S / G], uint32_t *abuf, 
 //
 // S limbs of radix 2^B hold the caller's `limbs` 32-bit words (B*S >= 32*limbs).
 template <int S, int G, int B>
-__global__ __launch_bounds__(64) void k_modexp(const uint32_t *__restrict__ base,
+__global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_modexp(const uint32_t *__restrict__ base,
                                                const uint32_t *__restrict__ exp,
                                                const uint32_t *__restrict__ mod,
                                                uint32_t *out, unsigned long long count, int limbs, int w,
@@ -426,6 +467,7 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
         if (r == 0) stage[i] = v;
     };
     uint32_t high[L];
+    Ar::load(other, (half ? p : q) + hoff, hl, 0, live);     // reloaded: not kept live across the loop
     Ar::mul_wide(high, mq, other, lds, sink);
 #pragma unroll
     for (int k = 0; k < L; ++k) stage[H + r * L + k] = high[k];

@@ -206,20 +206,100 @@ __device__ __forceinline__ uint32_t racc_normalise(uint32_t (&w)[S / G], const u
     return top ? ((own != 0) | k | k2) : 0u;
 }
 
+// Redundant: limbs below 2^B + 2^(64-2B) holding the accumulator's value,
+// for values below 2^(B*S) (nothing leaves the group's top lane).  Two rounds
+// of "keep the low B bits, hand the rest to the next position": after the
+// first every position is below 2^B + 2^(64-B), after the second below
+// 2^B + 2^(64-2B).  Every position is independent within a round, so the
+// dependency chain is a few instructions long instead of one carry chain
+// through all S limbs; a Montgomery product accepts such limbs as inputs.
+template <int S, int G, int B>
+__device__ __forceinline__ void racc_lazy(uint32_t (&w)[S / G], const uint64_t (&acc)[S / G])
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+    uint64_t v[L];
+    {
+        uint64_t hi[L];
+#pragma unroll
+        for (int j = 0; j < L; ++j) hi[j] = acc[j] >> B;
+        const uint32_t in_lo = grp_from_below<G>((uint32_t)hi[L - 1]);
+        const uint32_t in_hi = grp_from_below<G>((uint32_t)(hi[L - 1] >> 32));
+        v[0] = (uint64_t)((uint32_t)acc[0] & M) + (((uint64_t)in_hi << 32) | in_lo);
+#pragma unroll
+        for (int j = 1; j < L; ++j) v[j] = (uint64_t)((uint32_t)acc[j] & M) + hi[j - 1];
+    }
+    uint32_t h2[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) h2[j] = (uint32_t)(v[j] >> B);
+    const uint32_t in2 = grp_from_below<G>(h2[L - 1]);
+    w[0] = ((uint32_t)v[0] & M) + in2;
+#pragma unroll
+    for (int j = 1; j < L; ++j) w[j] = ((uint32_t)v[j] & M) + h2[j - 1];
+}
+
 // ---- Montgomery product, radix 2^B -----------------------------------------
 //
 // r = a * b * 2^(-B*S) mod n for a < 2^(BS) in registers and b < n in the
 // group's slot of LDS buffer bbuf (or a < n, b < 2^(BS)); n0inv = -n^-1 mod 2^B.
+//
+// LAZY: no final subtraction and redundant output limbs (racc_lazy).  For
+// a, b < 2n the result a*b/R + m*n/R is below 2n as long as R > 4n, which
+// every width class gives with room to spare (R >= 2^10 * n), so a chain of
+// lazy products stays below 2n without ever comparing with n; inputs may
+// have redundant limbs (below 2^B + 2^(64-2B)): the products stay below
+// 2^(2B) * (1 + 2^-20) and the accumulator bound of the squeeze interval
+// holds with the same margin.  The canonical form is restored by one
+// non-lazy product (leaving the Montgomery domain does exactly that).
+// The L CIOS steps of one block: multiplier limbs bv[0 .. L) (already
+// broadcast to the group), accumulator positions rotating through acc.
 template <int S, int G, int B>
+__device__ __forceinline__ void rcios_block(uint64_t (&acc)[S / G], const uint32_t (&a)[S / G],
+                                            const uint32_t (&bv)[S / G], const uint32_t (&n)[S / G],
+                                            uint32_t n0inv)
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+#pragma unroll
+        for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * bv[k];
+        const int p0 = k % L, p1 = (k + 1) % L;
+        const uint32_t m = grp_bcast0<G>(((uint32_t)acc[p0] * n0inv) & M);
+#pragma unroll
+        for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)m * n[j];
+        acc[p1] += acc[p0] >> B;
+        // the group's lane 0 holds zero in its low B bits here
+        acc[p0] = grp_rot_down<G>((uint32_t)acc[p0] & M);
+    }
+}
+
+// Blocks between squeezes: two products per position per step.
+template <int B, int L>
+constexpr int rsqueeze_blocks()
+{
+    return (((1 << (64 - 2 * B)) - 2) / 2) / L;
+}
+
+template <int S, int G, int B, bool LAZY>
+__device__ __forceinline__ void rmont_finish(uint32_t (&r)[S / G], const uint64_t (&acc)[S / G],
+                                             const uint32_t (&n)[S / G])
+{
+    if constexpr (LAZY) {
+        racc_lazy<S, G, B>(r, acc);
+    } else {
+        const uint32_t top = racc_normalise<S, G, B>(r, acc);
+        rgrp_cond_sub<S, G, B>(r, top, n);
+    }
+}
+
+template <int S, int G, int B, bool LAZY = false>
 __device__ __forceinline__ void rmont_mul(uint32_t (&r)[S / G], const uint32_t (&a)[S / G], const uint32_t *bbuf,
                                           const uint32_t (&n)[S / G], uint32_t n0inv)
 {
     using Ly = Layout<S, G>;
     constexpr int L = Ly::L, V = Ly::V;
-    constexpr uint32_t M = Radix<B>::MASK;
-    // steps between squeezes: two products per position per step
-    constexpr int KMAX = ((1 << (64 - 2 * B)) - 2) / 2;
-    constexpr int NB = KMAX / L;
+    constexpr int NB = rsqueeze_blocks<B, L>();
     static_assert(NB >= 1, "limbs per lane too large for the radix");
     const int g = grp_index<G>();
     uint64_t acc[L];
@@ -240,21 +320,53 @@ __device__ __forceinline__ void rmont_mul(uint32_t (&r)[S / G], const uint32_t (
 #pragma unroll
             for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
         }
+        rcios_block<S, G, B>(acc, a, bv, n, n0inv);
+    }
+    rmont_finish<S, G, B, LAZY>(r, acc, n);
+}
+
+// Value of lane K of this lane's group (G = 2 or 4: one DPP quad permute).
+template <int G, int K>
+__device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
+{
+    static_assert(G == 2 || G == 4, "quad permutes only");
+    if constexpr (G == 2) return dpp0<K == 0 ? DPP_QP_0022 : DPP_QP_1133>(v);
+    else return dpp0<K * 0x55>(v);                    // quad_perm [K, K, K, K]
+}
+
+// Blocks Q .. G-1 of a squaring whose multiplier is the group's own
+// registers: block Q takes limbs Q*L .. Q*L+L-1, which lane Q holds.
+template <int S, int G, int B, int Q>
+struct RSqrBlocks {
+    static __device__ __forceinline__ void run(uint64_t (&acc)[S / G], const uint32_t (&a)[S / G],
+                                               const uint32_t (&n)[S / G], uint32_t n0inv)
+    {
+        if constexpr (Q < G) {
+            constexpr int L = S / G, NB = rsqueeze_blocks<B, L>();
+            if constexpr (Q > 0 && Q % NB == 0) racc_squeeze<S, G, B>(acc);
+            uint32_t bv[L];
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-#pragma unroll
-            for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * bv[k];
-            const int p0 = k % L, p1 = (k + 1) % L;
-            const uint32_t m = grp_bcast0<G>(((uint32_t)acc[p0] * n0inv) & M);
-#pragma unroll
-            for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)m * n[j];
-            acc[p1] += acc[p0] >> B;
-            // the group's lane 0 holds zero in its low B bits here
-            acc[p0] = grp_rot_down<G>((uint32_t)acc[p0] & M);
+            for (int k = 0; k < L; ++k) bv[k] = grp_bcast_lane<G, Q>(a[k]);
+            rcios_block<S, G, B>(acc, a, bv, n, n0inv);
+            RSqrBlocks<S, G, B, Q + 1>::run(acc, a, n, n0inv);
         }
     }
-    const uint32_t top = racc_normalise<S, G, B>(r, acc);
-    rgrp_cond_sub<S, G, B>(r, top, n);
+};
+
+// r = a * a * 2^(-B*S) mod n with the multiplier limbs broadcast from the
+// group's registers by DPP (no LDS round trip); G = 2 or 4.  Same bounds and
+// LAZY meaning as rmont_mul; r may alias a.
+template <int S, int G, int B, bool LAZY>
+__device__ __forceinline__ void rmont_sqr_reg(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
+                                              const uint32_t (&n)[S / G], uint32_t n0inv)
+{
+    constexpr int L = S / G;
+    static_assert(rsqueeze_blocks<B, L>() >= 1, "limbs per lane too large for the radix");
+    uint64_t acc[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[j] = 0;
+    RSqrBlocks<S, G, B, 0>::run(acc, a, n, n0inv);
+    rmont_finish<S, G, B, LAZY>(r, acc, n);
 }
 
 // (low, high) = init + a * b (no reduction), b in LDS; lane 0 of the group

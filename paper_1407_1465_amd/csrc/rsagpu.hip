@@ -27,15 +27,17 @@ static const int kS29[] = {0, 0, 0, 0, 18, 28, 36, 56, 72, 112, 144};
 static const int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 
 // Default plan per class: limb radix 2^B, lanes per exponentiation G (limbs
-// per lane L = S / G) and window bits w.  From 512-bit operands up the
-// reduced radix 2^29 wins (one v_mad_u64_u32 per product, no carry handling,
-// despite ~21% more limb products); below, radix 2^32.  kind 0 = plain exponentiation,
-// kind 1 = CRT half.  L stays near 8 so the per-step cross-lane work is
-// amortised over 2L products, and the window is the largest whose 2^w
-// operand buffers per wave (2^w * 256 * L bytes of LDS) still let 8 waves
-// share a CU's 160 KiB: with fewer resident waves the dependency chain of
-// each Montgomery step (product, m, broadcast, products) is no longer hidden,
-// which costs far more than the extra multiplications of a narrower window.
+// per lane L = S / G) and window bits w, measured on large batches.  From
+// 512-bit operands up the reduced radix 2^29 wins (one v_mad_u64_u32 per
+// product, no carry handling, despite ~21% more limb products); below, radix
+// 2^32.  kind 0 = plain exponentiation, kind 1 = CRT half.  Two effects pull
+// against each other: more limbs per lane amortise the per-step cross-lane
+// work (broadcast of m, the limb that moves down) over 2L products and give
+// each wave more independent multiplications, while the LDS table
+// (2^w * 256 * L bytes per wave) and the registers limit the waves a CU holds.
+// For 1024-bit halves L = 18 (G = 2) with a 3-bit window (one wave per SIMD)
+// beats L = 9 (G = 4) at two waves per SIMD; for full 1024-bit exponents
+// L = 18 with a 2-bit window at two waves per SIMD is best.
 struct Plan {
     int B;
     int G;
@@ -43,9 +45,9 @@ struct Plan {
 };
 static const Plan kDefault[2][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 4, 2}, {29, 8, 3},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 2, 2}, {29, 8, 3},
      {29, 8, 2}, {29, 16, 3}, {29, 16, 2}},
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 4, 3}, {29, 8, 3},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 2, 3}, {29, 8, 3},
      {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
 };
 

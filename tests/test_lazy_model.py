@@ -1,0 +1,209 @@
+"""CPU model of the radix-2^29 lane-group Montgomery product.
+
+The GPU kernel keeps every limb position in a 64-bit accumulator and never
+checks for overflow; it relies on two bounds:
+
+* the squeeze interval (every 31 steps for B = 29) keeps each accumulator
+  below 2^64 even when the inputs carry redundant limbs;
+* lazy products (no final subtraction, redundant output limbs) keep a chain
+  of products below 2n when R > 4n, so the exponentiation never compares
+  with n and one canonical product at the end restores [0, n).
+
+This model replays the kernel's position arithmetic lane by lane (the same
+steps in the same order: products into rotating registers, m from lane 0,
+carry of the lowest register into the next, low bits moved one lane down,
+squeeze at block boundaries, lazy or full normalisation) on Python integers
+and asserts both bounds at every addition, then checks the results against
+Python's own modular arithmetic.  It is a check of the kernel's design, not
+of the kernel: the GPU parity tests compare the kernel itself with the
+oracle.
+"""
+import random
+
+import pytest
+
+MASK64 = (1 << 64) - 1
+
+
+def n0inv_of(n0, B):
+    # -n0^-1 mod 2^B
+    return (-pow(n0, -1, 1 << B)) % (1 << B)
+
+
+def to_limbs(x, S, B):
+    return [(x >> (B * i)) & ((1 << B) - 1) for i in range(S)]
+
+
+def value(limbs, B):
+    return sum(l << (B * i) for i, l in enumerate(limbs))
+
+
+class Model:
+    def __init__(self, S, G, B=29):
+        assert S % G == 0
+        self.S, self.G, self.B, self.L = S, G, B, S // G
+        self.M = (1 << B) - 1
+        self.KMAX = ((1 << (64 - 2 * B)) - 2) // 2
+        self.NB = self.KMAX // self.L
+        self.max_acc = 0
+
+    def _add(self, acc, g, r, v):
+        acc[g][r] += v
+        self.max_acc = max(self.max_acc, acc[g][r])
+        assert acc[g][r] <= MASK64, "accumulator overflow"
+
+    def _squeeze(self, acc):
+        G, L, B, M = self.G, self.L, self.B, self.M
+        cs = []
+        for g in range(G):
+            top = g == G - 1
+            c = [a >> B for a in acc[g]]
+            if top:
+                c[L - 1] = 0
+            for j in range(L):
+                if not (j == L - 1 and top):
+                    acc[g][j] &= M
+            for j in range(L - 1, 0, -1):
+                self._add(acc, g, j, c[j - 1])
+            cs.append(c[L - 1])
+        for g in range(G):
+            self._add(acc, g, 0, cs[g - 1] if g > 0 else 0)
+
+    def _lazy(self, acc):
+        G, L, B, M = self.G, self.L, self.B, self.M
+        his = [[a >> B for a in acc[g]] for g in range(G)]
+        v = [[0] * L for _ in range(G)]
+        for g in range(G):
+            v[g][0] = (acc[g][0] & M) + (his[g - 1][L - 1] if g > 0 else 0)
+            for j in range(1, L):
+                v[g][j] = (acc[g][j] & M) + his[g][j - 1]
+        # nothing may leave the group's top lane
+        assert his[G - 1][L - 1] == 0
+        h2 = [[x >> B for x in v[g]] for g in range(G)]
+        assert h2[G - 1][L - 1] == 0
+        w = []
+        for g in range(G):
+            w.append((v[g][0] & M) + (h2[g - 1][L - 1] if g > 0 else 0))
+            for j in range(1, L):
+                w.append((v[g][j] & M) + h2[g][j - 1])
+        return w
+
+    def mont_mul(self, a, b, n, lazy=True):
+        """a, b, n: S limbs each (a, b possibly redundant).  Returns limbs."""
+        S, G, L, B = self.S, self.G, self.L, self.B
+        acc = self.product_loop(a, b, n)
+        if lazy:
+            return self._lazy(acc)
+        # full normalisation and one conditional subtraction
+        v = sum(acc[g][j] << (B * (g * L + j)) for g in range(G) for j in range(L))
+        nv = value(n, B)
+        if v >= nv:
+            v -= nv
+        assert v < nv
+        return to_limbs(v, S, B)
+
+    def product_loop(self, a, b, n):
+        """The S steps of the product; returns the accumulators [lane][register]."""
+        S, G, L, B, M = self.S, self.G, self.L, self.B, self.M
+        ninv = n0inv_of(n[0], B)
+        acc = [[0] * L for _ in range(G)]
+        blk = 0
+        for i0 in range(0, S, L):
+            if blk == self.NB:
+                self._squeeze(acc)
+                blk = 0
+            for k in range(L):
+                bi = b[i0 + k]
+                for g in range(G):
+                    for j in range(L):
+                        self._add(acc, g, (j + k) % L, a[g * L + j] * bi)
+                p0, p1 = k % L, (k + 1) % L
+                m = (((acc[0][p0] & 0xFFFFFFFF) * ninv) & 0xFFFFFFFF) & M
+                for g in range(G):
+                    for j in range(L):
+                        self._add(acc, g, (j + k) % L, m * n[g * L + j])
+                for g in range(G):
+                    self._add(acc, g, p1, acc[g][p0] >> B)
+                low = [acc[g][p0] & M for g in range(G)]
+                assert low[0] == 0, "lowest position not cleared by m*n"
+                for g in range(G):
+                    acc[g][p0] = low[g + 1] if g + 1 < G else low[0]
+            blk += 1
+        return acc
+
+
+def rand_modulus(rng, bits):
+    return rng.getrandbits(bits) | (1 << (bits - 1)) | (1 << (bits - 2)) | 1
+
+
+@pytest.mark.parametrize("S,G,bits", [(18, 2, 512), (36, 4, 1024), (36, 2, 1024), (28, 4, 768)])
+def test_lazy_chain_matches_python(S, G, bits):
+    """A chain of lazy products (squarings and products with a fixed-window
+    table, as in the exponentiation) stays below 2n with bounded limbs and no
+    accumulator overflow; one canonical product at the end gives x^e mod n."""
+    rng = random.Random(S * 1000 + G + bits)
+    B = 29
+    md = Model(S, G, B)
+    R = 1 << (B * S)
+    for _ in range(2):
+        n = rand_modulus(rng, bits)
+        nl = to_limbs(n, S, B)
+        x = rng.randrange(n)
+        xt = to_limbs(x * R % n, S, B)
+        w = 3
+        table = [None, xt]
+        for i in range(2, 1 << w):
+            table.append(md.mont_mul(table[-1], xt, nl))
+        e = rng.getrandbits(48) | (1 << 47)
+        digits = []
+        t = e
+        while t:
+            digits.append(t & ((1 << w) - 1))
+            t >>= w
+        A = table[digits[-1]]
+        for d in reversed(digits[:-1]):
+            for _ in range(w):
+                A = md.mont_mul(A, A, nl)
+                assert value(A, B) < 2 * n
+                assert max(A) < (1 << B) + (1 << (64 - 2 * B))
+            if d:
+                A = md.mont_mul(A, table[d], nl)
+                assert value(A, B) < 2 * n
+        one = [1] + [0] * (S - 1)
+        out = md.mont_mul(A, one, nl, lazy=False)
+        assert value(out, B) == pow(x, e, n)
+
+
+@pytest.mark.parametrize("S,G", [(18, 2), (36, 2), (36, 4), (56, 4), (72, 8), (144, 16)])
+def test_accumulator_bound_with_extreme_limbs(S, G):
+    """Largest limbs a lazy product can hand on (2^29 + 63) with the largest
+    modulus limbs: the squeeze interval keeps every accumulator below 2^64
+    (the bound depends on limb sizes only, so this is the worst case)."""
+    B = 29
+    md = Model(S, G, B)
+    big = (1 << B) + (1 << (64 - 2 * B)) - 1
+    a = [big] * S
+    n = [(1 << B) - 1] * S
+    # synthetic inputs whose value exceeds 2^(B*S): only the product loop
+    # (every addition asserts the 64-bit bound)
+    md.product_loop(a, a, n)
+    assert md.max_acc < (1 << 64)
+    assert md.max_acc > (1 << 61)   # within a factor 8 of the limit: the check is meaningful
+
+
+def test_lazy_output_bound_is_tight_enough():
+    """Redundant output limbs stay below 2^29 + 2^6 over many random lazy
+    products with inputs close to 2n."""
+    rng = random.Random(7)
+    B, S, G = 29, 18, 2
+    md = Model(S, G, B)
+    for _ in range(20):
+        n = rand_modulus(rng, 512)
+        nl = to_limbs(n, S, B)
+        a = to_limbs(2 * n - 1 - rng.randrange(1000), S, B)
+        b = to_limbs(2 * n - 1 - rng.randrange(1000), S, B)
+        r = md.mont_mul(a, b, nl)
+        R = 1 << (B * S)
+        assert value(r, B) % n == value(a, B) * value(b, B) * pow(R, -1, n) % n
+        assert value(r, B) < 2 * n
+        assert max(r) < (1 << B) + (1 << 6)
