@@ -95,8 +95,11 @@ int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *
  * in (radix_bits = 32, or 29 for the reduced-radix kernels whose 64-bit
  * accumulators need no carry handling), the kernel's limb count in that
  * radix (padded_limbs), lanes per exponentiation (G), limbs per lane
- * (padded_limbs / G), fixed-window width (bits of exponent per table lookup,
- * paper Section 3.6.4) and the LDS bytes per 64-lane workgroup.
+ * (padded_limbs / G), window width in exponent bits and the LDS bytes per
+ * 64-lane workgroup.  Radix-2^29 plans with 2 or 4 lanes per exponentiation
+ * use a sliding window over the 2^(window_bits-1) odd powers (paper Section
+ * 3.6.5); all others a fixed window with a 2^window_bits - 1 entry table
+ * (Section 3.6.4).
  * kind: 0 = plain exponentiation, 1 = CRT half (modulus of `limbs` limbs).
  * Inputs and outputs are 32-bit limbs whatever the radix.  Pure host query.
  */
@@ -114,8 +117,9 @@ int rsa_get_plan(int limbs, int kind, rsa_plan *plan);
 /*
  * Overrides the plan of the width class that `limbs` maps to (kind as in
  * rsa_get_plan): (radix_bits, lanes_per_op) must name a compiled kernel
- * instance for that class, 2 <= window_bits <= 7, and 2^window_bits operand
- * buffers must fit 64 KiB of LDS.  All three zero restores the default.
+ * instance for that class, 2 <= window_bits <= 7, and the plan's LDS
+ * (lds_bytes of rsa_get_plan) must fit 64 KiB.  All three zero restores the
+ * default.
  * Used by the tuner; affects calls issued afterwards from any thread.
  * Pure host call.
  */

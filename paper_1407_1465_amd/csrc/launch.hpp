@@ -30,8 +30,25 @@ typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const 
 // Workgroups of an ops kernel resident per CU at window w (occupancy query).
 typedef int (*ops_occupancy)(int kind, int w);
 
-// LDS bytes of one 64-lane workgroup: 2^w operand buffers of S * (64 / G) words.
-inline size_t lds_bytes_for(int S, int G, int w) { return (size_t)(1u << w) * (size_t)S * (size_t)(64 / G) * 4u; }
+// Instances whose exponentiation runs the sliding window over odd powers
+// (radix 2^29 with 2 or 4 lanes per group, where every product of the loop
+// takes its multiplier from registers); the others run the fixed window.
+__host__ __device__ constexpr bool sliding_window(int B, int G) { return B != 32 && (G == 2 || G == 4); }
+
+// Operand buffers of S * (64 / G) words in one 64-lane workgroup's LDS:
+// fixed window w: the operand buffer and T[1 .. 2^w - 1]; sliding window w:
+// the 2^(w-1) odd powers (the operand buffer of the code outside the
+// exponentiation shares their space), at least 4 buffers either way (Montgomery
+// setup and Garner's staging use up to 3).
+__host__ __device__ constexpr int lds_entries(int B, int G, int w)
+{
+    return sliding_window(B, G) ? ((1 << (w - 1)) > 4 ? (1 << (w - 1)) : 4) : (1 << w);
+}
+
+inline size_t lds_bytes_for(int S, int G, int B, int w)
+{
+    return (size_t)lds_entries(B, G, w) * (size_t)S * (size_t)(64 / G) * 4u;
+}
 
 template <int S, int G, int B>
 hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32_t *mod, uint32_t *out,

@@ -12,7 +12,7 @@ hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32
 {
     const size_t ng = 64 / G;
     const size_t blocks = (count + ng - 1) / ng;
-    hipLaunchKernelGGL((k_modexp<S, G, B>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(S, G, w), stream, base,
+    hipLaunchKernelGGL((k_modexp<S, G, B>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(S, G, B, w), stream, base,
                        exp, mod, out, (unsigned long long)count, limbs, w, errs);
     return hipGetLastError();
 }
@@ -24,7 +24,7 @@ hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, c
 {
     const size_t pairs = 64 / G / 2;
     const size_t blocks = (count + pairs - 1) / pairs;
-    hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(H, G, w), stream, c, p, q,
+    hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(H, G, B, w), stream, c, p, q,
                        dp, dq, qinv, out, (unsigned long long)count, hl, w, errs);
     return hipGetLastError();
 }
@@ -35,7 +35,7 @@ hipError_t launch_setup(const uint32_t *const *mods, const uint32_t *const *mult
 {
     const int ng = 64 / G;
     const int blocks = (count + ng - 1) / ng;
-    hipLaunchKernelGGL((k_setup<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, 2), stream, mods, mults,
+    hipLaunchKernelGGL((k_setup<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, B, 2), stream, mods, mults,
                        words, outs, count);
     return hipGetLastError();
 }
@@ -45,7 +45,7 @@ hipError_t launch_ops_enc(const KeyDev *keys, const OpDesc *ops, const unsigned 
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                           hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_ops_enc<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, w), stream, keys, ops,
+    hipLaunchKernelGGL((k_ops_enc<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, B, w), stream, keys, ops,
                        list, count, counter, in_pool, out_pool, w);
     return hipGetLastError();
 }
@@ -55,7 +55,7 @@ hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned 
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                           hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, w), stream, keys, ops,
+    hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, B, w), stream, keys, ops,
                        list, count, counter, in_pool, out_pool, w);
     return hipGetLastError();
 }
@@ -64,7 +64,7 @@ template <int S, int G, int B>
 int ops_blocks_per_cu(int kind, int w)
 {
     int nb = 0;
-    const size_t lds = lds_bytes_for(S, G, w);
+    const size_t lds = lds_bytes_for(S, G, B, w);
     hipError_t e = kind == 0
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_enc<S, G, B>), 64, lds)
         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B>), 64, lds);

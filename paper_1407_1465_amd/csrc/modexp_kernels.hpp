@@ -13,6 +13,7 @@
 
 #include "group_bn.hpp"
 #include "radix_bn.hpp"
+#include "launch.hpp"
 
 // Minimum waves per SIMD a plain exponentiation kernel is compiled for (the
 // register budget per lane is 512 / waves).  With 14 or more limbs per lane
@@ -161,29 +162,17 @@ __device__ __forceinline__ void mont_mul_reg(uint32_t (&r)[S / G], const uint32_
     Arith<S, G, B>::mont_mul(r, a, abuf, n, n0inv);
 }
 
-// A = A^2 * R^-1 mod n through the operand buffer.
+// A = A^2 * R^-1 mod n through the operand buffer (lazy: below 2n with
+// redundant limbs, see rmont_mul).
 template <int S, int G, int B>
 __device__ __forceinline__ void mont_sqr(uint32_t (&A)[S / G], uint32_t *abuf, const uint32_t (&n)[S / G],
-                                         uint32_t n0inv)
+                                         uint32_t n0inv, bool lazy = false)
 {
-    mont_mul_reg<S, G, B>(A, A, A, abuf, n, n0inv);
-}
-
-// Lazy form of mont_sqr (result below 2n, limbs possibly redundant).  In
-// radix 2^29 with 2 or 4 lanes per group the multiplier comes straight from
-// the group's registers (DPP quad permutes), skipping the LDS round trip.
-template <int S, int G, int B>
-__device__ __forceinline__ void mont_sqr_lazy(uint32_t (&A)[S / G], uint32_t *abuf, const uint32_t (&n)[S / G],
-                                              uint32_t n0inv)
-{
-    if constexpr (B != 32 && (G == 2 || G == 4)) {
-        rmont_sqr_reg<S, G, B, true>(A, A, n, n0inv);
-    } else {
-        lds_sync();
-        lds_put<S, G>(abuf, A);
-        lds_sync();
-        Arith<S, G, B>::mont_mul_lazy(A, A, abuf, n, n0inv);
-    }
+    lds_sync();
+    lds_put<S, G>(abuf, A);
+    lds_sync();
+    if (lazy) Arith<S, G, B>::mont_mul_lazy(A, A, abuf, n, n0inv);
+    else Arith<S, G, B>::mont_mul(A, A, abuf, n, n0inv);
 }
 
 // Montgomery constants of an odd modulus n > 1 in radix 2^B, R = 2^(B*S):
@@ -259,7 +248,7 @@ __device__ __forceinline__ uint32_t exp_digit(const uint32_t *ep, int elimbs, in
 // start.  Every product here is lazy: A and the table stay below 2n in
 // redundant limbs, and the caller's from_mont makes the result canonical.
 template <int S, int G, int B>
-__device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
+__device__ __forceinline__ void group_modexp_fixed(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
                                              const uint32_t *ep, int elimbs, bool use_exp,
                                              const uint32_t (&n)[S / G], uint32_t n0inv,
                                              const uint32_t (&one)[S / G], uint32_t *lds, int w)
@@ -313,7 +302,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     }
     for (int win = nwin - 2; win >= 0; --win) {
         d = use_exp ? exp_digit(ep, elimbs, win * w, w) : 0u;
-        for (int s = 0; s < w; ++s) mont_sqr_lazy<S, G, B>(A, abuf, n, n0inv);
+        for (int s = 0; s < w; ++s) mont_sqr<S, G, B>(A, abuf, n, n0inv, true);
         if (__ballot(d != 0u)) {
             uint32_t t[L];
             Ar::mont_mul_lazy(t, A, tbl + ((d ? d : 1u) - 1) * Ly::WORDS, n, n0inv);
@@ -321,6 +310,163 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
             for (int k = 0; k < L; ++k) A[k] = d ? t[k] : A[k];
         }
     }
+}
+
+// Exponent bits of one group, scanned from the top: `hi:lo` holds words kw
+// and kw - 1 (bit positions 32*(kw-1) .. 32*kw+31) and `pre` word kw - 2,
+// loaded a word ahead of its use.
+struct ExpBits {
+    const uint32_t *ep;
+    int elimbs;
+    int kw;
+    uint64_t bits;
+    uint32_t pre;
+
+    __device__ __forceinline__ uint32_t word(int k) const { return (k >= 0 && k < elimbs) ? ep[k] : 0u; }
+    __device__ __forceinline__ void start(int top)
+    {
+        kw = top >> 5;
+        bits = ((uint64_t)word(kw) << 32) | word(kw - 1);
+        pre = word(kw - 2);
+    }
+    // Makes bit `pos` (<= the previous pos) fall in the high word.
+    __device__ __forceinline__ void seek(int pos)
+    {
+        if (pos >= 0 && (pos >> 5) < kw) {
+            bits = (bits << 32) | pre;
+            --kw;
+            pre = word(kw - 2);
+        }
+    }
+    // Bits lo .. hi (hi - lo < 32, hi in the high word, lo >= 32*(kw-1)).
+    __device__ __forceinline__ uint32_t field(int hi, int lo) const
+    {
+        const int off = lo - 32 * (kw - 1);
+        const uint32_t len = (uint32_t)(hi - lo + 1);
+        return (uint32_t)(bits >> off) & (uint32_t)((1ull << len) - 1ull);
+    }
+};
+
+// A = x^e mod n in Montgomery form (same contract as group_modexp_fixed) by
+// the left-to-right sliding window of Section 3.6.5 with windows of up to w
+// bits: table of odd powers T[k] = x^(2k+1), k < 2^(w-1), in LDS; a zero bit
+// costs one squaring, a window of value v (odd) and length l costs l
+// squarings and one product with T[(v-1)/2]; the leading window initialises
+// A.  Each group runs its own schedule; the wave executes one Montgomery
+// product per slot for all its groups, a squaring or a table product per
+// group (the multiplier is selected per group), until every group is done.
+// Multipliers come from registers (DPP broadcast), so the loop holds a single
+// copy of the product.  Products are lazy as in group_modexp_fixed.
+template <int S, int G, int B>
+__device__ __forceinline__ void group_modexp_sliding(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
+                                                     const uint32_t *ep, int elimbs, bool use_exp,
+                                                     const uint32_t (&n)[S / G], uint32_t n0inv,
+                                                     const uint32_t (&one)[S / G], uint32_t *lds, int w)
+{
+    using Ly = Layout<S, G>;
+    constexpr int L = Ly::L;
+    uint32_t *tbl = lds;                        // entry k at tbl + k * WORDS
+    const int g = grp_index<G>();
+
+    // odd powers: T[0] = x, T[k] = T[k-1] * x^2
+    {
+        uint32_t x2[L], cur[L];
+        rmont_mul_regs<S, G, B, true>(x2, xt, xt, n, n0inv);
+#pragma unroll
+        for (int k = 0; k < L; ++k) cur[k] = xt[k];
+        lds_sync();                             // earlier users of the operand buffer are done
+        lds_put<S, G>(tbl, cur);
+        const int tsize = 1 << (w - 1);
+        for (int i = 1; i < tsize; ++i) {
+            rmont_mul_regs<S, G, B, true>(cur, cur, x2, n, n0inv);
+            lds_put<S, G>(tbl + i * Ly::WORDS, cur);
+        }
+        lds_sync();
+    }
+
+    // this group's exponent length (its lanes scan slices of the words)
+    uint32_t ebits = 0;
+    if (use_exp) {
+        const int per = (elimbs + G - 1) / G;
+        const int r = grp_lane<G>();
+        for (int k = 0; k < per; ++k) {
+            const int li = r * per + k;
+            const uint32_t v = li < elimbs ? ep[li] : 0u;
+            if (v) ebits = (uint32_t)(32 * li + 32 - __clz(v));
+        }
+    }
+    ebits = grp_max<G>(ebits);
+
+    ExpBits eb{ep, use_exp ? elimbs : 0, 0, 0, 0};
+    int pos = (int)ebits - 1;                   // next bit to scan
+    int sq = 0, mi = -1;                        // pending squarings, pending table index
+    // Takes the next window at pos: a zero bit (one squaring) or a window
+    // ending in a one (its length in squarings, then T[(v-1)/2]).
+    auto next_window = [&]() {
+        eb.seek(pos);
+        if (((uint32_t)(eb.bits >> (pos - 32 * (eb.kw - 1))) & 1u) == 0u) {
+            sq = 1;
+            mi = -1;
+            pos -= 1;
+            return;
+        }
+        const int lo0 = pos - w + 1 > 0 ? pos - w + 1 : 0;
+        uint32_t v = eb.field(pos, lo0);
+        const int tz = __builtin_ctz(v);
+        v >>= tz;
+        sq = pos - (lo0 + tz) + 1;
+        mi = (int)(v >> 1);
+        pos = lo0 + tz - 1;
+    };
+
+#pragma unroll
+    for (int k = 0; k < L; ++k) A[k] = one[k];
+    if (pos >= 0) {
+        eb.start(pos);
+        next_window();                          // the leading bit is one: a window
+        uint32_t t[L];
+        lds_get<S, G>(t, tbl + mi * Ly::WORDS, g);
+#pragma unroll
+        for (int k = 0; k < L; ++k) A[k] = t[k];
+        sq = 0;
+        mi = -1;
+        if (pos >= 0) next_window();
+    }
+    for (;;) {
+        const bool active = sq > 0 || mi >= 0;
+        if (!__ballot(active)) break;
+        const bool mul = sq == 0 && mi >= 0;
+        uint32_t b[L];
+#pragma unroll
+        for (int k = 0; k < L; ++k) b[k] = A[k];
+        if (__ballot(mul)) {
+            uint32_t tb[L];                     // this lane's limbs of T[mi]
+            lds_get<S, G>(tb, tbl + (mul ? mi : 0) * Ly::WORDS, g);
+#pragma unroll
+            for (int k = 0; k < L; ++k) b[k] = mul ? tb[k] : b[k];
+        }
+        uint32_t t[L];
+        rmont_mul_regs<S, G, B, true>(t, A, b, n, n0inv);
+#pragma unroll
+        for (int k = 0; k < L; ++k) A[k] = active ? t[k] : A[k];
+        if (mul) mi = -1;
+        else if (sq > 0) --sq;
+        if (sq == 0 && mi < 0 && pos >= 0) next_window();
+    }
+}
+
+// A = x^e mod n in Montgomery form: sliding window where every product takes
+// its multiplier from registers, fixed window otherwise.
+template <int S, int G, int B>
+__device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
+                                             const uint32_t *ep, int elimbs, bool use_exp,
+                                             const uint32_t (&n)[S / G], uint32_t n0inv,
+                                             const uint32_t (&one)[S / G], uint32_t *lds, int w)
+{
+    if constexpr (sliding_window(B, G))
+        group_modexp_sliding<S, G, B>(A, xt, ep, elimbs, use_exp, n, n0inv, one, lds, w);
+    else
+        group_modexp_fixed<S, G, B>(A, xt, ep, elimbs, use_exp, n, n0inv, one, lds, w);
 }
 
 // A = A * R^-1 mod n (leave Montgomery form).

@@ -334,38 +334,40 @@ __device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
     else return dpp0<K * 0x55>(v);                    // quad_perm [K, K, K, K]
 }
 
-// Blocks Q .. G-1 of a squaring whose multiplier is the group's own
-// registers: block Q takes limbs Q*L .. Q*L+L-1, which lane Q holds.
+// Blocks Q .. G-1 of a product whose multiplier b is held in the group's
+// registers like a: block Q takes limbs Q*L .. Q*L+L-1, which lane Q holds.
 template <int S, int G, int B, int Q>
-struct RSqrBlocks {
+struct RRegBlocks {
     static __device__ __forceinline__ void run(uint64_t (&acc)[S / G], const uint32_t (&a)[S / G],
-                                               const uint32_t (&n)[S / G], uint32_t n0inv)
+                                               const uint32_t (&b)[S / G], const uint32_t (&n)[S / G],
+                                               uint32_t n0inv)
     {
         if constexpr (Q < G) {
             constexpr int L = S / G, NB = rsqueeze_blocks<B, L>();
             if constexpr (Q > 0 && Q % NB == 0) racc_squeeze<S, G, B>(acc);
             uint32_t bv[L];
 #pragma unroll
-            for (int k = 0; k < L; ++k) bv[k] = grp_bcast_lane<G, Q>(a[k]);
+            for (int k = 0; k < L; ++k) bv[k] = grp_bcast_lane<G, Q>(b[k]);
             rcios_block<S, G, B>(acc, a, bv, n, n0inv);
-            RSqrBlocks<S, G, B, Q + 1>::run(acc, a, n, n0inv);
+            RRegBlocks<S, G, B, Q + 1>::run(acc, a, b, n, n0inv);
         }
     }
 };
 
-// r = a * a * 2^(-B*S) mod n with the multiplier limbs broadcast from the
-// group's registers by DPP (no LDS round trip); G = 2 or 4.  Same bounds and
-// LAZY meaning as rmont_mul; r may alias a.
+// r = a * b * 2^(-B*S) mod n with both operands in the group's registers and
+// the multiplier limbs broadcast by DPP (no LDS round trip); G = 2 or 4.
+// Same bounds and LAZY meaning as rmont_mul; r may alias a or b.
 template <int S, int G, int B, bool LAZY>
-__device__ __forceinline__ void rmont_sqr_reg(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
-                                              const uint32_t (&n)[S / G], uint32_t n0inv)
+__device__ __forceinline__ void rmont_mul_regs(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
+                                               const uint32_t (&b)[S / G], const uint32_t (&n)[S / G],
+                                               uint32_t n0inv)
 {
     constexpr int L = S / G;
     static_assert(rsqueeze_blocks<B, L>() >= 1, "limbs per lane too large for the radix");
     uint64_t acc[L];
 #pragma unroll
     for (int j = 0; j < L; ++j) acc[j] = 0;
-    RSqrBlocks<S, G, B, 0>::run(acc, a, n, n0inv);
+    RRegBlocks<S, G, B, 0>::run(acc, a, b, n, n0inv);
     rmont_finish<S, G, B, LAZY>(r, acc, n);
 }
 

@@ -35,9 +35,10 @@ static const int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 // work (broadcast of m, the limb that moves down) over 2L products and give
 // each wave more independent multiplications, while the LDS table
 // (2^w * 256 * L bytes per wave) and the registers limit the waves a CU holds.
-// For 1024-bit halves L = 18 (G = 2) with a 3-bit window (one wave per SIMD)
-// beats L = 9 (G = 4) at two waves per SIMD; for full 1024-bit exponents
-// L = 18 with a 2-bit window at two waves per SIMD is best.
+// For 1024-bit halves L = 18 (G = 2) at one wave per SIMD beats L = 9 (G = 4)
+// at two; for full 1024-bit exponents L = 18 at two waves per SIMD is best.
+// With 2 or 4 lanes per group the window is a sliding window over odd powers
+// (2^(w-1) LDS buffers), so w = 4 there costs the LDS of a fixed 3-bit window.
 struct Plan {
     int B;
     int G;
@@ -45,9 +46,9 @@ struct Plan {
 };
 static const Plan kDefault[2][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 2, 2}, {29, 8, 3},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 3},
      {29, 8, 2}, {29, 16, 3}, {29, 16, 2}},
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 3}, {29, 4, 3}, {29, 2, 3}, {29, 8, 3},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
      {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
 };
 
@@ -189,7 +190,7 @@ extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)
     plan->lanes_per_op = r.inst->G;
     plan->limbs_per_lane = r.inst->S / r.inst->G;
     plan->window_bits = r.w;
-    plan->lds_bytes = (int)lds_bytes_for(r.inst->S, r.inst->G, r.w);
+    plan->lds_bytes = (int)lds_bytes_for(r.inst->S, r.inst->G, r.inst->B, r.w);
     return RSA_OK;
 }
 
@@ -207,7 +208,7 @@ extern "C" int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_o
     const Instance *in = find_instance(i, radix_bits, lanes_per_op);
     if (!in) return RSA_EINVAL;
     if (window_bits < 2 || window_bits > 7) return RSA_EINVAL;
-    if (lds_bytes_for(in->S, in->G, window_bits) > 64 * 1024) return RSA_EINVAL;
+    if (lds_bytes_for(in->S, in->G, in->B, window_bits) > 64 * 1024) return RSA_EINVAL;
     g_plan[kind][i].store(pack(Plan{radix_bits, lanes_per_op, window_bits}));
     return RSA_OK;
 }

@@ -81,3 +81,24 @@ def test_plans_are_consistent():
             rsagpu.set_plan(*bad)
     rsagpu.set_plan(32, 1, 0, 0, 0)
     assert rsagpu.get_plan(32, 1) == default
+
+
+def test_plan_lds_sizes():
+    """LDS per 64-lane workgroup: fixed window w = 2^w buffers of S*(64/G)
+    words; sliding window (radix 2^29, 2 or 4 lanes) = 2^(w-1) odd powers,
+    at least 4 buffers."""
+    from paper_1407_1465_amd import rsagpu
+    cases = [
+        ((32, 1, 29, 2, 4), 8 * 36 * 32 * 4),     # sliding, 8 odd powers
+        ((32, 1, 29, 2, 3), 4 * 36 * 32 * 4),     # sliding, minimum of 4 buffers
+        ((32, 1, 29, 4, 5), 16 * 36 * 16 * 4),    # sliding, 16 odd powers
+        ((32, 1, 32, 8, 3), 8 * 32 * 8 * 4),      # fixed, radix 2^32
+        ((64, 0, 29, 8, 3), 8 * 72 * 8 * 4),      # fixed, 8 lanes per group
+    ]
+    try:
+        for args, lds in cases:
+            rsagpu.set_plan(*args)
+            assert rsagpu.get_plan(args[0], args[1]).lds_bytes == lds, args
+    finally:
+        for limbs, kind in ((32, 1), (64, 0)):
+            rsagpu.set_plan(limbs, kind, 0, 0, 0)
