@@ -42,19 +42,59 @@ def fixed_window_montmuls(ebits: int, w: int) -> int:
     return (nwin - 1) * (w + 1) + (1 << w)
 
 
+def sliding_window_montmuls(e: int, w: int) -> int:
+    """Montgomery products of the left-to-right sliding window over odd
+    powers for exponent e: the table (x^2 and 2^(w-1) - 1 products; for
+    exponents of at most 64 bits only up to the largest power used), one
+    squaring per bit below the leading window, one product per further
+    window (a window ends in a one bit and spans at most w bits)."""
+    if e == 0:
+        return 0
+    pos, sq, mul, first, used = e.bit_length() - 1, 0, 0, True, 0
+    while pos >= 0:
+        if not (e >> pos) & 1:
+            sq, pos = sq + 1, pos - 1
+            continue
+        lo = max(pos - w + 1, 0)
+        while not (e >> lo) & 1:
+            lo += 1
+        used = max(used, ((e >> lo) & ((1 << (pos - lo + 1)) - 1)) // 2 + 1)
+        if not first:
+            sq, mul = sq + pos - lo + 1, mul + 1
+        first, pos = False, lo - 1
+    tsize = (1 << (w - 1)) if e.bit_length() > 64 else used
+    return sq + mul + (tsize if tsize > 1 else 0)
+
+
+def montmuls(e: int, plan) -> int:
+    """Montgomery products of one exponentiation with the schedule the plan
+    runs (sliding window for radix-2^29 plans with 2 or 4 lanes per group)."""
+    if plan.radix_bits == 29 and plan.lanes_per_op in (2, 4):
+        return sliding_window_montmuls(e, plan.window_bits)
+    return fixed_window_montmuls(e.bit_length(), plan.window_bits)
+
+
+def per_key_sum(key_of, fn) -> int:
+    """sum(fn(k) for k in key_of), evaluating fn once per distinct key."""
+    import collections
+    keys = key_of.tolist() if hasattr(key_of, "tolist") else key_of
+    return sum(n * fn(k) for k, n in collections.Counter(map(lambda x: tuple(x) if isinstance(x, list) else x,
+                                                             keys)).items())
+
+
 def mont_products(s: int) -> int:
     """32x32-bit products of one Montgomery product of s 32-bit limbs."""
     return 2 * s * s + s
 
 
-def crt_products(key, w: int) -> int:
+def crt_products(key, plan) -> int:
     h = key.limbs // 2
-    mm = fixed_window_montmuls(key.dp.bit_length(), w) + fixed_window_montmuls(key.dq.bit_length(), w)
+    mm = montmuls(key.dp, plan) + montmuls(key.dq, plan)
     return mm * mont_products(h) + mont_products(h) + h * h
 
 
-def modexp_products(key, ebits: int, w: int) -> int:
-    return fixed_window_montmuls(ebits, w) * mont_products(key.limbs)
+def modexp_products(key, e: int, plan) -> int:
+    return montmuls(e, plan) * mont_products(key.limbs)
 
 
 def timed(fn, steps, warmup, torch):
@@ -72,16 +112,19 @@ def timed(fn, steps, warmup, torch):
     return ev0.elapsed_time(ev1) / steps, time.perf_counter() - wall0
 
 
+# Sources the plain exponentiation and CRT kernels are compiled from (device
+# arithmetic, kernels, launch configuration); host-only files are left out.
+KERNEL_SOURCES = ("group_bn.hpp", "radix_bn.hpp", "modexp_kernels.hpp", "launch.hpp", "launch_impl.hpp")
+
+
 def kernel_src_hash():
-    """sha256 over the library's kernel and host sources (csrc)."""
-    import glob
+    """sha256 over the sources the plain kernels are built from."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1407_1465_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "*.hip")) +
-                    glob.glob(os.path.join(csrc, "*.def"))):
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -183,7 +226,7 @@ def main():
             back = rsagpu.modexp(out[idx].contiguous(), dev(e_h)[idx].contiguous(), dev(n_h)[idx].contiguous())
             if not torch.equal(back, c[idx]):
                 raise SystemExit("round-trip check failed")
-            products = sum(crt_products(wl.keys[k], plan.window_bits) for k in wl.key_of.tolist())
+            products = per_key_sum(wl.key_of, lambda k: crt_products(wl.keys[k], plan))
             # the same batch as one launch per key (plain form, no cross-key batching)
             per_key = []
             for j in range(len(wl.keys)):
@@ -214,7 +257,7 @@ def main():
             out = torch.empty_like(m)
             plan = rsagpu.get_plan(L, 0)
             ms, wall = timed(lambda: rsagpu.modexp(m, e, n, out=out), args.steps, args.warmup, torch)
-            products = sum(modexp_products(wl.keys[k], 17, plan.window_bits) for k in wl.key_of.tolist())
+            products = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].e, plan))
             line.update(metric="2048-bit modexp/sec (encrypt, e=65537) on 1 GPU", unit="encryptions/s",
                         config={"workload": "rsa2048-encrypt", "keys": len(wl.keys), "messages": count,
                                 "radix_bits": plan.radix_bits, "window_bits": plan.window_bits,
@@ -236,8 +279,7 @@ def main():
         out = torch.empty_like(c)
         plan = rsagpu.get_plan(L, 0)
         ms, wall = timed(lambda: rsagpu.modexp(c, d, n, out=out), args.steps, args.warmup, torch)
-        products = sum(modexp_products(wl.keys[k], wl.keys[k].d.bit_length(), plan.window_bits)
-                       for k in wl.key_of.tolist())
+        products = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].d, plan))
         line.update(metric="%d-bit modexp/sec (full-d decrypt) on 1 GPU" % (32 * L), unit="decryptions/s",
                     config={"workload": wl.name + "-decrypt", "messages": count, "radix_bits": plan.radix_bits,
                             "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
@@ -267,11 +309,12 @@ def main():
         torch.cuda.synchronize()
         if not torch.equal(back, inp) or rsagpu.device_errors() != 0:
             raise SystemExit("mixed batch round trip failed")
-        products = 0
-        for kind, kid in zip(wl.kinds.tolist(), wl.key_ids.tolist()):
+        def op_products(kk):
+            kind, kid = kk
             k = wl.keys[kid]
             pl = rsagpu.get_plan(k.limbs // 2 if kind else k.limbs, kind)
-            products += crt_products(k, pl.window_bits) if kind else modexp_products(k, 17, pl.window_bits)
+            return crt_products(k, pl) if kind else modexp_products(k, k.e, pl)
+        products = per_key_sum(np.stack([wl.kinds, wl.key_ids], 1).tolist(), lambda kk: op_products(tuple(kk)))
         line.update(metric="mixed-size RSA ops/sec (1024-4096-bit, half CRT decrypt) on 1 GPU", unit="ops/s",
                     config={"workload": wl.name, "ops": nops, "keys": len(wl.keys)})
         line["roofline"] = roofline(products, ms, "k_ops_* (all buckets)")

@@ -349,7 +349,9 @@ struct ExpBits {
 
 // A = x^e mod n in Montgomery form (same contract as group_modexp_fixed) by
 // the left-to-right sliding window of Section 3.6.5 with windows of up to w
-// bits: table of odd powers T[k] = x^(2k+1), k < 2^(w-1), in LDS; a zero bit
+// bits: table of odd powers T[k] = x^(2k+1), k < 2^(w-1), in LDS (for
+// exponents of at most 64 bits only the powers the wave uses: 65537 needs
+// x alone, 16 squarings and one product, as Fig. 5's binary method); a zero bit
 // costs one squaring, a window of value v (odd) and length l costs l
 // squarings and one product with T[(v-1)/2]; the leading window initialises
 // A.  Each group runs its own schedule; the wave executes one Montgomery
@@ -367,22 +369,6 @@ __device__ __forceinline__ void group_modexp_sliding(uint32_t (&A)[S / G], const
     constexpr int L = Ly::L;
     uint32_t *tbl = lds;                        // entry k at tbl + k * WORDS
     const int g = grp_index<G>();
-
-    // odd powers: T[0] = x, T[k] = T[k-1] * x^2
-    {
-        uint32_t x2[L], cur[L];
-        rmont_mul_regs<S, G, B, true>(x2, xt, xt, n, n0inv);
-#pragma unroll
-        for (int k = 0; k < L; ++k) cur[k] = xt[k];
-        lds_sync();                             // earlier users of the operand buffer are done
-        lds_put<S, G>(tbl, cur);
-        const int tsize = 1 << (w - 1);
-        for (int i = 1; i < tsize; ++i) {
-            rmont_mul_regs<S, G, B, true>(cur, cur, x2, n, n0inv);
-            lds_put<S, G>(tbl + i * Ly::WORDS, cur);
-        }
-        lds_sync();
-    }
 
     // this group's exponent length (its lanes scan slices of the words)
     uint32_t ebits = 0;
@@ -418,6 +404,43 @@ __device__ __forceinline__ void group_modexp_sliding(uint32_t (&A)[S / G], const
         mi = (int)(v >> 1);
         pos = lo0 + tz - 1;
     };
+
+    // Table size: all 2^(w-1) odd powers, or for short exponents (public
+    // exponents such as 65537) only those the wave's schedules use, found by
+    // one scan of the windows without products.
+    int tsize = 1 << (w - 1);
+    if (wave_max(ebits) <= 64u) {
+        int used = 0;
+        if (pos >= 0) {
+            eb.start(pos);
+            while (pos >= 0) {
+                next_window();
+                used = mi + 1 > used ? mi + 1 : used;
+            }
+        }
+        tsize = (int)wave_max((uint32_t)used);
+        pos = (int)ebits - 1;
+        sq = 0;
+        mi = -1;
+    }
+
+    // odd powers: T[0] = x, T[k] = T[k-1] * x^2
+    {
+        uint32_t cur[L];
+#pragma unroll
+        for (int k = 0; k < L; ++k) cur[k] = xt[k];
+        lds_sync();                             // earlier users of the operand buffer are done
+        lds_put<S, G>(tbl, cur);
+        if (tsize > 1) {
+            uint32_t x2[L];
+            rmont_mul_regs<S, G, B, true>(x2, xt, xt, n, n0inv);
+            for (int i = 1; i < tsize; ++i) {
+                rmont_mul_regs<S, G, B, true>(cur, cur, x2, n, n0inv);
+                lds_put<S, G>(tbl + i * Ly::WORDS, cur);
+            }
+        }
+        lds_sync();
+    }
 
 #pragma unroll
     for (int k = 0; k < L; ++k) A[k] = one[k];

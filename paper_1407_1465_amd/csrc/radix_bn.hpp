@@ -4,10 +4,13 @@
 // per lane), but every limb holds B < 32 bits in a 32-bit word.  A product of
 // two limbs is below 2^(2B), so a 64-bit accumulator absorbs 2^(64 - 2B)
 // products without overflow: the Montgomery loop is one v_mad_u64_u32 per
-// product with no carry detection at all.  For B = 29 that is 64 products; the
-// CIOS loop adds two products per limb position per step, so the positions
-// are partially normalised (each keeps its low B bits and hands the rest to
-// the next position) every 31 steps or fewer.
+// product with no carry detection at all.  For B = 29 that is 64 products.
+// The CIOS loop adds two products per register per step, and every register
+// is drained once every L steps (when it holds the lane's lowest position, its
+// low B bits move one lane down and the rest, below 2^(64-B), moves to the
+// next register), so a register never holds more than 2L products plus two
+// small terms: L <= 31 limbs per lane keeps every accumulator below 2^64 with
+// no normalisation inside the product.
 //
 // Integers enter and leave in the caller's 32-bit-limb format; conversion
 // happens at load time (each lane reads the 32-bit words that hold its limbs)
@@ -144,28 +147,6 @@ __device__ __forceinline__ uint32_t rgrp_bitlen(const uint32_t (&x)[S / G])
 
 // ---- accumulator normalisation -----------------------------------------
 
-// Partial: every position keeps its low B bits and passes the rest to the
-// next position; the top position of a lane passes it to the lane above (the
-// group's top lane keeps it, it is the part beyond S limbs).  The value is
-// unchanged and every position drops below 2^B + 2^(64-B).
-template <int S, int G, int B>
-__device__ __forceinline__ void racc_squeeze(uint64_t (&acc)[S / G])
-{
-    constexpr int L = S / G;
-    const bool top = grp_lane<G>() == G - 1;
-    uint64_t c[L];
-#pragma unroll
-    for (int j = 0; j < L; ++j) c[j] = acc[j] >> B;
-    if (top) c[L - 1] = 0;
-#pragma unroll
-    for (int j = 0; j < L; ++j) acc[j] = (j == L - 1 && top) ? acc[j] : (acc[j] & Radix<B>::MASK);
-#pragma unroll
-    for (int j = L - 1; j > 0; --j) acc[j] += c[j - 1];
-    const uint32_t rlo = grp_from_below<G>((uint32_t)c[L - 1]);
-    const uint32_t rhi = grp_from_below<G>((uint32_t)(c[L - 1] >> 32));
-    acc[0] += ((uint64_t)rhi << 32) | rlo;
-}
-
 // Full: canonical B-bit limbs in w, returns the group's overflow beyond S
 // limbs (meaningful in the top lane).
 template <int S, int G, int B>
@@ -239,18 +220,7 @@ __device__ __forceinline__ void racc_lazy(uint32_t (&w)[S / G], const uint64_t (
 }
 
 // ---- Montgomery product, radix 2^B -----------------------------------------
-//
-// r = a * b * 2^(-B*S) mod n for a < 2^(BS) in registers and b < n in the
-// group's slot of LDS buffer bbuf (or a < n, b < 2^(BS)); n0inv = -n^-1 mod 2^B.
-//
-// LAZY: no final subtraction and redundant output limbs (racc_lazy).  For
-// a, b < 2n the result a*b/R + m*n/R is below 2n as long as R > 4n, which
-// every width class gives with room to spare (R >= 2^10 * n), so a chain of
-// lazy products stays below 2n without ever comparing with n; inputs may
-// have redundant limbs (below 2^B + 2^(64-2B)): the products stay below
-// 2^(2B) * (1 + 2^-20) and the accumulator bound of the squeeze interval
-// holds with the same margin.  The canonical form is restored by one
-// non-lazy product (leaving the Montgomery domain does exactly that).
+
 // The L CIOS steps of one block: multiplier limbs bv[0 .. L) (already
 // broadcast to the group), accumulator positions rotating through acc.
 template <int S, int G, int B>
@@ -274,11 +244,14 @@ __device__ __forceinline__ void rcios_block(uint64_t (&acc)[S / G], const uint32
     }
 }
 
-// Blocks between squeezes: two products per position per step.
+// Limbs per lane for which no accumulator can overflow: a register gathers
+// at most 2L products below 2^(2B) * (1 + 2^-20) (inputs may carry redundant
+// limbs) plus a carry below 2^(64-B) and a limb below 2^B+2^(64-2B) between
+// two drains.
 template <int B, int L>
-constexpr int rsqueeze_blocks()
+constexpr bool rdrain_fits()
 {
-    return (((1 << (64 - 2 * B)) - 2) / 2) / L;
+    return L >= 1 && L <= ((1 << (64 - 2 * B)) - 2) / 2;
 }
 
 template <int S, int G, int B, bool LAZY>
@@ -293,25 +266,30 @@ __device__ __forceinline__ void rmont_finish(uint32_t (&r)[S / G], const uint64_
     }
 }
 
+// r = a * b * 2^(-B*S) mod n for a < 2^(BS) in registers and b < n in the
+// group's slot of LDS buffer bbuf (or a < n, b < 2^(BS)); n0inv = -n^-1 mod 2^B.
+//
+// LAZY: no final subtraction and redundant output limbs (racc_lazy).  For
+// a, b < 2n the result a*b/R + m*n/R is below 2n as long as R > 4n, which
+// every width class gives with room to spare (R >= 2^10 * n), so a chain of
+// lazy products stays below 2n without ever comparing with n; inputs may
+// have redundant limbs (below 2^B + 2^(64-2B)): the products stay below
+// 2^(2B) * (1 + 2^-20), which the accumulator bound (rdrain_fits) allows
+// for.  The canonical form is restored by one non-lazy product (leaving the
+// Montgomery domain does exactly that).
 template <int S, int G, int B, bool LAZY = false>
 __device__ __forceinline__ void rmont_mul(uint32_t (&r)[S / G], const uint32_t (&a)[S / G], const uint32_t *bbuf,
                                           const uint32_t (&n)[S / G], uint32_t n0inv)
 {
     using Ly = Layout<S, G>;
     constexpr int L = Ly::L, V = Ly::V;
-    constexpr int NB = rsqueeze_blocks<B, L>();
-    static_assert(NB >= 1, "limbs per lane too large for the radix");
+    static_assert(rdrain_fits<B, L>(), "limbs per lane too large for the radix");
     const int g = grp_index<G>();
     uint64_t acc[L];
 #pragma unroll
     for (int j = 0; j < L; ++j) acc[j] = 0;
 
-    int blk = 0;
-    for (int i0 = 0; i0 < S; i0 += L, ++blk) {
-        if (blk == NB) {
-            racc_squeeze<S, G, B>(acc);
-            blk = 0;
-        }
+    for (int i0 = 0; i0 < S; i0 += L) {
         uint32_t bv[L];
 #pragma unroll
         for (int k = 0; k < L; k += V) {
@@ -343,8 +321,7 @@ struct RRegBlocks {
                                                uint32_t n0inv)
     {
         if constexpr (Q < G) {
-            constexpr int L = S / G, NB = rsqueeze_blocks<B, L>();
-            if constexpr (Q > 0 && Q % NB == 0) racc_squeeze<S, G, B>(acc);
+            constexpr int L = S / G;
             uint32_t bv[L];
 #pragma unroll
             for (int k = 0; k < L; ++k) bv[k] = grp_bcast_lane<G, Q>(b[k]);
@@ -363,7 +340,7 @@ __device__ __forceinline__ void rmont_mul_regs(uint32_t (&r)[S / G], const uint3
                                                uint32_t n0inv)
 {
     constexpr int L = S / G;
-    static_assert(rsqueeze_blocks<B, L>() >= 1, "limbs per lane too large for the radix");
+    static_assert(rdrain_fits<B, L>(), "limbs per lane too large for the radix");
     uint64_t acc[L];
 #pragma unroll
     for (int j = 0; j < L; ++j) acc[j] = 0;
@@ -380,19 +357,13 @@ __device__ __forceinline__ void rmul_wide(uint32_t (&high)[S / G], const uint32_
     using Ly = Layout<S, G>;
     constexpr int L = Ly::L, V = Ly::V;
     constexpr uint32_t M = Radix<B>::MASK;
-    constexpr int KMAX = (1 << (64 - 2 * B)) - 2;
-    constexpr int NB = KMAX / L;
+    static_assert(rdrain_fits<B, L>(), "limbs per lane too large for the radix");
     const int g = grp_index<G>();
     uint64_t acc[L];
 #pragma unroll
     for (int j = 0; j < L; ++j) acc[j] = init[j];
 
-    int blk = 0;
-    for (int i0 = 0; i0 < S; i0 += L, ++blk) {
-        if (blk == NB) {
-            racc_squeeze<S, G, B>(acc);
-            blk = 0;
-        }
+    for (int i0 = 0; i0 < S; i0 += L) {
         uint32_t bv[L];
 #pragma unroll
         for (int k = 0; k < L; k += V) {

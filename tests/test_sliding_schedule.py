@@ -9,9 +9,13 @@ on a squaring and grows by 2k+1 on a table product) and checks that the
 schedule reaches e, stays within the table, and does the expected number of
 products.  The GPU parity tests check the kernels' results themselves.
 """
+import os
 import random
+import sys
 
 import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 
 class ExpBits:
@@ -104,6 +108,31 @@ def test_schedule_reaches_exponent(w):
         assert top_mi < (1 << (w - 1))               # within the odd-power table
         # every bit below the leading window costs exactly one squaring
         assert nsq <= e.bit_length() - 1
+
+
+def table_size(e, w):
+    """Odd powers the kernel builds: all 2^(w-1), or for exponents of at most
+    64 bits the largest index the schedule uses plus one (its pre-scan)."""
+    if e.bit_length() > 64:
+        return 1 << (w - 1)
+    return schedule(e, w)[3] + 1 if e else 0
+
+
+@pytest.mark.parametrize("w", [2, 3, 4, 5])
+def test_short_exponent_table_and_count(w):
+    # 65537 = 2^16 + 1: x alone, 16 squarings and one product (binary method)
+    acc, nsq, nmul, top = schedule(65537, w)
+    assert (acc, nsq, nmul, top) == (65537, 16, 1, 0)
+    assert table_size(65537, w) == 1
+    import bench
+    assert bench.sliding_window_montmuls(65537, w) == 17
+    rng = random.Random(100 + w)
+    for _ in range(200):
+        e = rng.getrandbits(rng.choice([3, 17, 40, 64, 65, 200, 1024])) | 1
+        acc, nsq, nmul, top = schedule(e, w)
+        ts = table_size(e, w)
+        assert top < ts <= (1 << (w - 1))
+        assert bench.sliding_window_montmuls(e, w) == nsq + nmul + (ts if ts > 1 else 0)
 
 
 def test_schedule_zero_exponent():
