@@ -312,7 +312,7 @@ def main():
         def op_products(kk):
             kind, kid = kk
             k = wl.keys[kid]
-            pl = rsagpu.get_plan(k.limbs // 2 if kind else k.limbs, kind)
+            pl = rsagpu.get_plan(k.limbs // 2 if kind else k.limbs, kind + 2)      # ops-batch plans
             return crt_products(k, pl) if kind else modexp_products(k, k.e, pl)
         products = per_key_sum(np.stack([wl.kinds, wl.key_ids], 1).tolist(), lambda kk: op_products(tuple(kk)))
         line.update(metric="mixed-size RSA ops/sec (1024-4096-bit, half CRT decrypt) on 1 GPU", unit="ops/s",

@@ -100,7 +100,10 @@ int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *
  * use a sliding window over the 2^(window_bits-1) odd powers (paper Section
  * 3.6.5); all others a fixed window with a 2^window_bits - 1 entry table
  * (Section 3.6.4).
- * kind: 0 = plain exponentiation, 1 = CRT half (modulus of `limbs` limbs).
+ * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
+ * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
+ * operations inside rsa_ops_batch (separate plans: its buckets are smaller
+ * and run side by side).
  * Inputs and outputs are 32-bit limbs whatever the radix.  Pure host query.
  */
 typedef struct {

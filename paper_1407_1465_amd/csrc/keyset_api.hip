@@ -320,7 +320,7 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
             const int b = cls * 2 + kind;
             const int width = kind == 0 ? class_width(cls) : class_width(cls) / 2;
             Resolved r;
-            if (!resolve(width, kind, &r)) return RSA_ELIMBS;
+            if (!resolve(width, kind + 2, &r)) return RSA_ELIMBS;         // the ops-batch plans
             int per = r.inst->blocks_per_cu(kind, r.w);
             if (per <= 0) per = 1;
             const int blocks = per * cus;

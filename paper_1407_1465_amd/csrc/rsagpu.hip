@@ -44,8 +44,18 @@ struct Plan {
     int G;
     int w;
 };
-static const Plan kDefault[2][kNumClasses] = {
+//
+// Kinds 2 and 3 are the same operations inside rsa_ops_batch, whose buckets
+// are usually far smaller than a plain batch and run side by side: there a
+// narrower group (more waves per operation) and a smaller LDS footprint (room
+// for the other buckets' waves) pay off.
+static const int kKinds = 4;
+static const Plan kDefault[kKinds][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 3},
+     {29, 8, 2}, {29, 16, 3}, {29, 16, 2}},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
+     {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
     {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 3},
      {29, 8, 2}, {29, 16, 3}, {29, 16, 2}},
     {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
@@ -56,12 +66,12 @@ static int pack(const Plan &p) { return p.B << 16 | p.G << 8 | p.w; }
 static Plan unpack(int v) { return Plan{v >> 16, (v >> 8) & 0xFF, v & 0xFF}; }
 
 // Current plans; overridable with rsa_set_plan.
-static std::atomic<int> g_plan[2][kNumClasses];
+static std::atomic<int> g_plan[kKinds][kNumClasses];
 static std::once_flag g_plan_once;
 
 static void init_plans()
 {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < kKinds; ++k)
         for (int i = 0; i < kNumClasses; ++i) g_plan[k][i].store(pack(kDefault[k][i]));
 }
 
@@ -181,7 +191,7 @@ extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const
 
 extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)
 {
-    if (!plan || (kind != 0 && kind != 1)) return RSA_EINVAL;
+    if (!plan || kind < 0 || kind >= kKinds) return RSA_EINVAL;
     if (limbs < 1 || limbs > RSA_MAX_LIMBS) return RSA_ELIMBS;
     Resolved r;
     if (!resolve(limbs, kind, &r)) return RSA_ELIMBS;
@@ -196,7 +206,7 @@ extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)
 
 extern "C" int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int window_bits)
 {
-    if (kind != 0 && kind != 1) return RSA_EINVAL;
+    if (kind < 0 || kind >= kKinds) return RSA_EINVAL;
     if (limbs < 1 || limbs > RSA_MAX_LIMBS) return RSA_ELIMBS;
     std::call_once(g_plan_once, init_plans);
     const int i = class_index(limbs);

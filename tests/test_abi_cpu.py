@@ -83,6 +83,28 @@ def test_plans_are_consistent():
     assert rsagpu.get_plan(32, 1) == default
 
 
+def test_ops_batch_plans_are_separate():
+    """Kinds 2 and 3 (operations inside rsa_ops_batch) have their own plans:
+    overriding one leaves the plain-call plan (kinds 0 and 1) alone."""
+    from paper_1407_1465_amd import rsagpu
+    plain = rsagpu.get_plan(32, 1)
+    try:
+        rsagpu.set_plan(32, 3, 29, 4, 3)
+        assert rsagpu.get_plan(32, 1) == plain
+        p = rsagpu.get_plan(32, 3)
+        assert (p.radix_bits, p.lanes_per_op, p.window_bits) == (29, 4, 3)
+        rsagpu.set_plan(64, 2, 29, 8, 2)
+        assert rsagpu.get_plan(64, 2).lanes_per_op == 8
+    finally:
+        rsagpu.set_plan(32, 3, 0, 0, 0)
+        rsagpu.set_plan(64, 2, 0, 0, 0)
+    for kind in (-1, 4):
+        with pytest.raises(Exception):
+            rsagpu.get_plan(32, kind)
+        with pytest.raises(Exception):
+            rsagpu.set_plan(32, kind, 29, 4, 3)
+
+
 def test_plan_lds_sizes():
     """LDS per 64-lane workgroup: fixed window w = 2^w buffers of S*(64/G)
     words; sliding window (radix 2^29, 2 or 4 lanes) = 2^(w-1) odd powers,
