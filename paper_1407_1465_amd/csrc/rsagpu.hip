@@ -53,13 +53,13 @@ static const int kKinds = 4;
 static const Plan kDefault[kKinds][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
     {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 3},
-     {29, 8, 2}, {29, 16, 3}, {29, 16, 2}},
+     {29, 4, 4}, {29, 16, 3}, {29, 16, 2}},
     {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
      {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 3},
-     {29, 8, 2}, {29, 16, 3}, {29, 16, 2}},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 4, 3}, {29, 8, 3},
+     {29, 4, 4}, {29, 16, 3}, {29, 16, 2}},
     {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
-     {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
+     {29, 8, 4}, {29, 16, 3}, {29, 16, 2}},
 };
 
 static int pack(const Plan &p) { return p.B << 16 | p.G << 8 | p.w; }
