@@ -57,8 +57,8 @@ static const Plan kDefault[kKinds][kNumClasses] = {
     {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
      {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
     {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 4, 3}, {29, 8, 3},
-     {29, 4, 4}, {29, 16, 3}, {29, 16, 2}},
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
+     {29, 4, 4}, {29, 8, 3}, {29, 16, 2}},
+    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {32, 4, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 4},
      {29, 8, 4}, {29, 16, 3}, {29, 16, 2}},
 };
 
