@@ -35,13 +35,6 @@ INT32_MUL_PEAK = 256 * 64 * 2.4e9
 METRIC = "2048-bit modexp/sec (CRT decrypt) on 1 GPU, %INT32-mul peak; p50/p99 latency"
 
 
-def fixed_window_montmuls(ebits: int, w: int) -> int:
-    """Montgomery products of the fixed-window method for an ebits-bit
-    exponent: (ceil(b/w) - 1)(w + 1) + 2^w."""
-    nwin = -(-ebits // w)
-    return (nwin - 1) * (w + 1) + (1 << w)
-
-
 def sliding_window_montmuls(e: int, w: int) -> int:
     """Montgomery products of the left-to-right sliding window over odd
     powers for exponent e: the table (x^2 and 2^(w-1) - 1 products; for
@@ -67,11 +60,8 @@ def sliding_window_montmuls(e: int, w: int) -> int:
 
 
 def montmuls(e: int, plan) -> int:
-    """Montgomery products of one exponentiation with the schedule the plan
-    runs (sliding window for radix-2^29 plans with 2 or 4 lanes per group)."""
-    if plan.radix_bits == 29 and plan.lanes_per_op in (2, 4):
-        return sliding_window_montmuls(e, plan.window_bits)
-    return fixed_window_montmuls(e.bit_length(), plan.window_bits)
+    """Montgomery products of one exponentiation with the plan's window."""
+    return sliding_window_montmuls(e, plan.window_bits)
 
 
 def per_key_sum(key_of, fn) -> int:

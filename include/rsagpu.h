@@ -95,11 +95,9 @@ int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *
  * in (radix_bits = 32, or 29 for the reduced-radix kernels whose 64-bit
  * accumulators need no carry handling), the kernel's limb count in that
  * radix (padded_limbs), lanes per exponentiation (G), limbs per lane
- * (padded_limbs / G), window width in exponent bits and the LDS bytes per
- * 64-lane workgroup.  Radix-2^29 plans with 2 or 4 lanes per exponentiation
- * use a sliding window over the 2^(window_bits-1) odd powers (paper Section
- * 3.6.5); all others a fixed window with a 2^window_bits - 1 entry table
- * (Section 3.6.4).
+ * (padded_limbs / G), window width in exponent bits (a sliding window over
+ * the 2^(window_bits-1) odd powers, paper Section 3.6.5) and the LDS bytes
+ * per 64-lane workgroup.
  * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
  * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
  * operations inside rsa_ops_batch (separate plans: its buckets are smaller

@@ -102,6 +102,17 @@ __device__ __forceinline__ uint32_t grp_bcast0(uint32_t v)
     } else return (uint32_t)__shfl((int)v, 0, G);
 }
 
+// Value of lane K of this lane's group (G = 1, 2 or 4: at most one DPP quad
+// permute).
+template <int G, int K>
+__device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
+{
+    static_assert(G == 1 || G == 2 || G == 4, "quad permutes only");
+    if constexpr (G == 1) return v;
+    else if constexpr (G == 2) return dpp0<K == 0 ? DPP_QP_0022 : DPP_QP_1133>(v);
+    else return dpp0<K * 0x55>(v);                    // quad_perm [K, K, K, K]
+}
+
 // Value of lane `src` of this lane's group (not on hot paths).
 template <int G>
 __device__ __forceinline__ uint32_t grp_bcast(uint32_t v, int src)
@@ -486,6 +497,29 @@ __device__ __forceinline__ uint32_t grp_normalise(uint32_t (&w)[S / G], const ui
 // group's slot of LDS buffer bbuf (or a < n and b < 2^(32S)), n odd.
 // Mode Wide (used for the plain product of the CRT recombination): no
 // reduction; the bottom limb of each step is handed to `sink` instead.
+// The L CIOS steps of one block in radix 2^32 (96-bit positions acc:hi),
+// multiplier limbs bv[0 .. L) already broadcast to the group.
+template <int S, int G>
+__device__ __forceinline__ void cios32_block(uint64_t (&acc)[S / G], uint32_t (&hi)[S / G],
+                                             const uint32_t (&a)[S / G], const uint32_t (&bv)[S / G],
+                                             const uint32_t (&n)[S / G], uint32_t n0inv)
+{
+    constexpr int L = S / G;
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        // position j of this step lives in register (j + k) % L
+        mac_row<L>(acc, hi, a, bv[k], k);
+        const int p0 = k % L, p1 = (k + 1) % L;
+        const uint32_t m = grp_bcast0<G>((uint32_t)acc[p0] * n0inv);
+        mac_row<L>(acc, hi, n, m, k);
+        add96(acc[p1], hi[p1], (uint32_t)(acc[p0] >> 32), hi[p0]);
+        // the bottom word of the group's lane 0 is zero here, so a
+        // rotation inside the group moves zero into the top lane
+        acc[p0] = grp_rot_down<G>((uint32_t)acc[p0]);
+        hi[p0] = 0;
+    }
+}
+
 template <int S, int G>
 __device__ __forceinline__ void mont_mul(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
                                          const uint32_t *bbuf, const uint32_t (&n)[S / G],
@@ -508,20 +542,44 @@ __device__ __forceinline__ void mont_mul(uint32_t (&r)[S / G], const uint32_t (&
 #pragma unroll
             for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
         }
+        cios32_block<S, G>(acc, hi, a, bv, n, n0inv);
+    }
+    const uint32_t top = grp_normalise<S, G>(r, acc, hi);
+    grp_cond_sub<S, G>(r, top, n);
+}
+
+// Blocks Q .. G-1 of a radix-2^32 product whose multiplier b is held in the
+// group's registers like a: block Q takes limbs Q*L .. Q*L+L-1 (lane Q).
+template <int S, int G, int Q>
+struct Regs32Blocks {
+    static __device__ __forceinline__ void run(uint64_t (&acc)[S / G], uint32_t (&hi)[S / G],
+                                               const uint32_t (&a)[S / G], const uint32_t (&b)[S / G],
+                                               const uint32_t (&n)[S / G], uint32_t n0inv)
+    {
+        if constexpr (Q < G) {
+            constexpr int L = S / G;
+            uint32_t bv[L];
 #pragma unroll
-        for (int k = 0; k < L; ++k) {
-            // position j of this step lives in register (j + k) % L
-            mac_row<L>(acc, hi, a, bv[k], k);
-            const int p0 = k % L, p1 = (k + 1) % L;
-            const uint32_t m = grp_bcast0<G>((uint32_t)acc[p0] * n0inv);
-            mac_row<L>(acc, hi, n, m, k);
-            add96(acc[p1], hi[p1], (uint32_t)(acc[p0] >> 32), hi[p0]);
-            // the bottom word of the group's lane 0 is zero here, so a
-            // rotation inside the group moves zero into the top lane
-            acc[p0] = grp_rot_down<G>((uint32_t)acc[p0]);
-            hi[p0] = 0;
+            for (int k = 0; k < L; ++k) bv[k] = grp_bcast_lane<G, Q>(b[k]);
+            cios32_block<S, G>(acc, hi, a, bv, n, n0inv);
+            Regs32Blocks<S, G, Q + 1>::run(acc, hi, a, b, n, n0inv);
         }
     }
+};
+
+// mont_mul with the multiplier in the group's registers (G = 1, 2 or 4):
+// no LDS round trip; r may alias a or b.
+template <int S, int G>
+__device__ __forceinline__ void mont_mul_regs(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
+                                              const uint32_t (&b)[S / G], const uint32_t (&n)[S / G],
+                                              uint32_t n0inv)
+{
+    constexpr int L = S / G;
+    uint64_t acc[L];
+    uint32_t hi[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) { acc[j] = 0; hi[j] = 0; }
+    Regs32Blocks<S, G, 0>::run(acc, hi, a, b, n, n0inv);
     const uint32_t top = grp_normalise<S, G>(r, acc, hi);
     grp_cond_sub<S, G>(r, top, n);
 }

@@ -30,19 +30,21 @@ typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const 
 // Workgroups of an ops kernel resident per CU at window w (occupancy query).
 typedef int (*ops_occupancy)(int kind, int w);
 
-// Instances whose exponentiation runs the sliding window over odd powers
-// (radix 2^29 with 2 or 4 lanes per group, where every product of the loop
-// takes its multiplier from registers); the others run the fixed window.
-__host__ __device__ constexpr bool sliding_window(int B, int G) { return B != 32 && (G == 2 || G == 4); }
+// Instances whose Montgomery products inside the exponentiation take the
+// multiplier from registers (1, 2 or 4 lanes per group: at most one DPP quad
+// permute per step); the others read it from LDS.
+__host__ __device__ constexpr bool register_products(int B, int G) { return G == 1 || G == 2 || G == 4; }
 
-// Operand buffers of S * (64 / G) words in one 64-lane workgroup's LDS:
-// fixed window w: the operand buffer and T[1 .. 2^w - 1]; sliding window w:
-// the 2^(w-1) odd powers (the operand buffer of the code outside the
-// exponentiation shares their space), at least 4 buffers either way (Montgomery
-// setup and Garner's staging use up to 3).
+// Operand buffers of S * (64 / G) words in one 64-lane workgroup's LDS for a
+// sliding window of w bits: the 2^(w-1) odd powers, plus the operand buffer
+// the LDS-multiplier products stage A through (with register products the
+// code before and after the exponentiation borrows the table's space for
+// it); at least 4 buffers (Montgomery setup and Garner's staging use up to 3).
 __host__ __device__ constexpr int lds_entries(int B, int G, int w)
 {
-    return sliding_window(B, G) ? ((1 << (w - 1)) > 4 ? (1 << (w - 1)) : 4) : (1 << w);
+    return ((1 << (w - 1)) + (register_products(B, G) ? 0 : 1)) > 4
+               ? ((1 << (w - 1)) + (register_products(B, G) ? 0 : 1))
+               : 4;
 }
 
 inline size_t lds_bytes_for(int S, int G, int B, int w)

@@ -51,6 +51,13 @@ struct Arith {
     {
         rmont_mul<S, G, B, true>(r, a, b, n, n0inv);
     }
+    // Lazy product with the multiplier in the group's registers (G = 2 or 4).
+    static __device__ __forceinline__ void mont_mul_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                              const uint32_t (&b)[L], const uint32_t (&n)[L],
+                                                              uint32_t n0inv)
+    {
+        rmont_mul_regs<S, G, B, true>(r, a, b, n, n0inv);
+    }
     template <typename Sink>
     static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
                                                     const uint32_t (&a)[L], const uint32_t *b, Sink sink)
@@ -100,6 +107,12 @@ struct Arith<S, G, 32> {
                                                          const uint32_t *b, const uint32_t (&n)[L], uint32_t n0inv)
     {
         rsagpu::mont_mul<S, G>(r, a, b, n, n0inv);
+    }
+    static __device__ __forceinline__ void mont_mul_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                              const uint32_t (&b)[L], const uint32_t (&n)[L],
+                                                              uint32_t n0inv)
+    {
+        rsagpu::mont_mul_regs<S, G>(r, a, b, n, n0inv);
     }
     template <typename Sink>
     static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
@@ -162,17 +175,12 @@ __device__ __forceinline__ void mont_mul_reg(uint32_t (&r)[S / G], const uint32_
     Arith<S, G, B>::mont_mul(r, a, abuf, n, n0inv);
 }
 
-// A = A^2 * R^-1 mod n through the operand buffer (lazy: below 2n with
-// redundant limbs, see rmont_mul).
+// A = A^2 * R^-1 mod n through the operand buffer.
 template <int S, int G, int B>
 __device__ __forceinline__ void mont_sqr(uint32_t (&A)[S / G], uint32_t *abuf, const uint32_t (&n)[S / G],
-                                         uint32_t n0inv, bool lazy = false)
+                                         uint32_t n0inv)
 {
-    lds_sync();
-    lds_put<S, G>(abuf, A);
-    lds_sync();
-    if (lazy) Arith<S, G, B>::mont_mul_lazy(A, A, abuf, n, n0inv);
-    else Arith<S, G, B>::mont_mul(A, A, abuf, n, n0inv);
+    mont_mul_reg<S, G, B>(A, A, A, abuf, n, n0inv);
 }
 
 // Montgomery constants of an odd modulus n > 1 in radix 2^B, R = 2^(B*S):
@@ -226,91 +234,6 @@ __device__ __forceinline__ void mont_setup(uint32_t (&one)[S / G], uint32_t (&r2
     }
 }
 
-// Fixed-window digit of an exponent: bits [pos, pos + w) (zero beyond elimbs).
-__device__ __forceinline__ uint32_t exp_digit(const uint32_t *ep, int elimbs, int pos, int w)
-{
-    const int li = pos >> 5, sh = pos & 31;
-    const uint32_t lo = li < elimbs ? ep[li] : 0u;
-    const uint32_t hi = (sh + w > 32 && li + 1 < elimbs) ? ep[li + 1] : 0u;
-    const uint64_t v = (((uint64_t)hi << 32) | lo) >> sh;
-    return (uint32_t)v & ((1u << w) - 1u);
-}
-
-// A = x^e mod n in Montgomery form, for xt = x*R mod n and an exponent e of
-// elimbs 32-bit words at ep (read only when use_exp).
-//
-// Left-to-right k-ary method (Section 3.6.4, Fig. 6) with k = w: table
-// T[i] = x^i (i = 1 .. 2^w - 1) in LDS, then, from the most significant
-// digit, w squarings followed by one product with T[digit].  The leading
-// digit initialises A directly (the w squarings of 1 are skipped); a zero
-// digit skips its product.  The window count is the wave's largest exponent
-// length, so groups with shorter exponents run on A = 1 until their digits
-// start.  Every product here is lazy: A and the table stay below 2n in
-// redundant limbs, and the caller's from_mont makes the result canonical.
-template <int S, int G, int B>
-__device__ __forceinline__ void group_modexp_fixed(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
-                                             const uint32_t *ep, int elimbs, bool use_exp,
-                                             const uint32_t (&n)[S / G], uint32_t n0inv,
-                                             const uint32_t (&one)[S / G], uint32_t *lds, int w)
-{
-    using Ly = Layout<S, G>;
-    using Ar = Arith<S, G, B>;
-    constexpr int L = Ly::L;
-    uint32_t *abuf = lds;
-    uint32_t *tbl = lds + Ly::WORDS;            // entry i at tbl + (i - 1) * WORDS
-    const int g = grp_index<G>();
-
-    // table T[1] = x, T[i] = T[i-1] * x
-    lds_sync();
-    lds_put<S, G>(tbl, xt);
-    uint32_t cur[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) cur[k] = xt[k];
-    lds_sync();
-    const int tsize = 1 << w;
-    for (int i = 2; i < tsize; ++i) {
-        Ar::mont_mul_lazy(cur, cur, tbl, n, n0inv);
-        lds_put<S, G>(tbl + (i - 1) * Ly::WORDS, cur);
-    }
-    lds_sync();
-
-    // exponent length in bits, maximised over the wave (the group's lanes
-    // share the exponent words; each lane scans a slice)
-    uint32_t ebits = 0;
-    if (use_exp) {
-        const int per = (elimbs + G - 1) / G;
-        const int r = grp_lane<G>();
-        for (int k = 0; k < per; ++k) {
-            const int li = r * per + k;
-            const uint32_t v = li < elimbs ? ep[li] : 0u;
-            if (v) ebits = (uint32_t)(32 * li + 32 - __clz(v));
-        }
-    }
-    const uint32_t maxbits = wave_max(ebits);
-    const int nwin = (int)((maxbits + (uint32_t)w - 1) / (uint32_t)w);
-
-#pragma unroll
-    for (int k = 0; k < L; ++k) A[k] = one[k];
-    if (nwin == 0) return;
-
-    uint32_t d = use_exp ? exp_digit(ep, elimbs, (nwin - 1) * w, w) : 0u;
-    {
-        uint32_t t[L];
-        lds_get<S, G>(t, tbl + ((d ? d : 1u) - 1) * Ly::WORDS, g);
-#pragma unroll
-        for (int k = 0; k < L; ++k) A[k] = d ? t[k] : A[k];
-    }
-    for (int win = nwin - 2; win >= 0; --win) {
-        d = use_exp ? exp_digit(ep, elimbs, win * w, w) : 0u;
-        for (int s = 0; s < w; ++s) mont_sqr<S, G, B>(A, abuf, n, n0inv, true);
-        if (__ballot(d != 0u)) {
-            uint32_t t[L];
-            Ar::mont_mul_lazy(t, A, tbl + ((d ? d : 1u) - 1) * Ly::WORDS, n, n0inv);
-#pragma unroll
-            for (int k = 0; k < L; ++k) A[k] = d ? t[k] : A[k];
-        }
-    }
-}
 
 // Exponent bits of one group, scanned from the top: `hi:lo` holds words kw
 // and kw - 1 (bit positions 32*(kw-1) .. 32*kw+31) and `pre` word kw - 2,
@@ -347,28 +270,43 @@ struct ExpBits {
     }
 };
 
-// A = x^e mod n in Montgomery form (same contract as group_modexp_fixed) by
-// the left-to-right sliding window of Section 3.6.5 with windows of up to w
-// bits: table of odd powers T[k] = x^(2k+1), k < 2^(w-1), in LDS (for
-// exponents of at most 64 bits only the powers the wave uses: 65537 needs
-// x alone, 16 squarings and one product, as Fig. 5's binary method); a zero bit
-// costs one squaring, a window of value v (odd) and length l costs l
-// squarings and one product with T[(v-1)/2]; the leading window initialises
-// A.  Each group runs its own schedule; the wave executes one Montgomery
-// product per slot for all its groups, a squaring or a table product per
-// group (the multiplier is selected per group), until every group is done.
-// Multipliers come from registers (DPP broadcast), so the loop holds a single
-// copy of the product.  Products are lazy as in group_modexp_fixed.
+// A = x^e mod n in Montgomery form, for xt = x*R mod n and an exponent e of
+// elimbs 32-bit words at ep (read only when use_exp), by the left-to-right
+// sliding window of Section 3.6.5 with windows of up to w bits: table of odd
+// powers T[k] = x^(2k+1), k < 2^(w-1), in LDS (for exponents of at most 64
+// bits only the powers the wave uses: 65537 needs x alone, 16 squarings and
+// one product, as Fig. 5's binary method); a zero bit costs one squaring, a
+// window of value v (odd) and length l costs l squarings and one product
+// with T[(v-1)/2]; the leading window initialises A.  Each group runs its own
+// schedule; the wave executes one Montgomery product per slot for all its
+// groups, a squaring or a table product per group (the multiplier is
+// selected per group), until every group is done, so the loop holds a single
+// copy of the product.  With register_products(B, G) the multiplier comes
+// from registers (DPP broadcast; the table starts at the LDS base); otherwise
+// A is staged through the operand buffer at the LDS base (the table follows
+// it) and each group's product reads its own multiplier there or in its
+// table entry.  Every product is lazy (A and the table stay below 2n in
+// redundant limbs); the caller's from_mont makes the result canonical.
 template <int S, int G, int B>
-__device__ __forceinline__ void group_modexp_sliding(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
+__device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
                                                      const uint32_t *ep, int elimbs, bool use_exp,
                                                      const uint32_t (&n)[S / G], uint32_t n0inv,
                                                      const uint32_t (&one)[S / G], uint32_t *lds, int w)
 {
     using Ly = Layout<S, G>;
+    using Ar = Arith<S, G, B>;
     constexpr int L = Ly::L;
-    uint32_t *tbl = lds;                        // entry k at tbl + k * WORDS
+    constexpr bool REG = register_products(B, G);
+    uint32_t *abuf = lds;                       // operand buffer (LDS-multiplier products)
+    uint32_t *tbl = REG ? lds : lds + Ly::WORDS;   // entry k at tbl + k * WORDS
     const int g = grp_index<G>();
+    // lazy product with a multiplier in registers (b) or in LDS (bl)
+    auto mul_regs = [&](uint32_t (&r)[L], const uint32_t (&a)[L], const uint32_t (&b)[L]) {
+        if constexpr (REG) Ar::mont_mul_regs_lazy(r, a, b, n, n0inv);
+    };
+    auto mul_lds = [&](uint32_t (&r)[L], const uint32_t (&a)[L], const uint32_t *bl) {
+        Ar::mont_mul_lazy(r, a, bl, n, n0inv);
+    };
 
     // this group's exponent length (its lanes scan slices of the words)
     uint32_t ebits = 0;
@@ -386,14 +324,20 @@ __device__ __forceinline__ void group_modexp_sliding(uint32_t (&A)[S / G], const
     ExpBits eb{ep, use_exp ? elimbs : 0, 0, 0, 0};
     int pos = (int)ebits - 1;                   // next bit to scan
     int sq = 0, mi = -1;                        // pending squarings, pending table index
-    // Takes the next window at pos: a zero bit (one squaring) or a window
+    // Takes the next window at pos: a run of zero bits (one squaring each,
+    // the run cut at the bottom of the bit buffer and at bit 0) or a window
     // ending in a one (its length in squarings, then T[(v-1)/2]).
     auto next_window = [&]() {
         eb.seek(pos);
-        if (((uint32_t)(eb.bits >> (pos - 32 * (eb.kw - 1))) & 1u) == 0u) {
-            sq = 1;
+        const int off = pos - 32 * (eb.kw - 1);           // 32 .. 63
+        if (((uint32_t)(eb.bits >> off) & 1u) == 0u) {
+            const uint64_t x = eb.bits << (63 - off);     // bit pos on top
+            int run = x ? __clzll(x) : 64;                // zeros from pos down (>= 1)
+            run = run < off ? run : off;
+            run = run < pos + 1 ? run : pos + 1;
+            sq = run;
             mi = -1;
-            pos -= 1;
+            pos -= run;
             return;
         }
         const int lo0 = pos - w + 1 > 0 ? pos - w + 1 : 0;
@@ -433,9 +377,17 @@ __device__ __forceinline__ void group_modexp_sliding(uint32_t (&A)[S / G], const
         lds_put<S, G>(tbl, cur);
         if (tsize > 1) {
             uint32_t x2[L];
-            rmont_mul_regs<S, G, B, true>(x2, xt, xt, n, n0inv);
+            if constexpr (REG) {
+                mul_regs(x2, xt, xt);
+            } else {
+                lds_sync();
+                mul_lds(x2, xt, tbl);
+                lds_put<S, G>(abuf, x2);
+                lds_sync();
+            }
             for (int i = 1; i < tsize; ++i) {
-                rmont_mul_regs<S, G, B, true>(cur, cur, x2, n, n0inv);
+                if constexpr (REG) mul_regs(cur, cur, x2);
+                else mul_lds(cur, cur, abuf);
                 lds_put<S, G>(tbl + i * Ly::WORDS, cur);
             }
         }
@@ -459,37 +411,30 @@ __device__ __forceinline__ void group_modexp_sliding(uint32_t (&A)[S / G], const
         const bool active = sq > 0 || mi >= 0;
         if (!__ballot(active)) break;
         const bool mul = sq == 0 && mi >= 0;
-        uint32_t b[L];
-#pragma unroll
-        for (int k = 0; k < L; ++k) b[k] = A[k];
-        if (__ballot(mul)) {
-            uint32_t tb[L];                     // this lane's limbs of T[mi]
-            lds_get<S, G>(tb, tbl + (mul ? mi : 0) * Ly::WORDS, g);
-#pragma unroll
-            for (int k = 0; k < L; ++k) b[k] = mul ? tb[k] : b[k];
-        }
         uint32_t t[L];
-        rmont_mul_regs<S, G, B, true>(t, A, b, n, n0inv);
+        if constexpr (REG) {
+            uint32_t b[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) b[k] = A[k];
+            if (__ballot(mul)) {
+                uint32_t tb[L];                 // this lane's limbs of T[mi]
+                lds_get<S, G>(tb, tbl + (mul ? mi : 0) * Ly::WORDS, g);
+#pragma unroll
+                for (int k = 0; k < L; ++k) b[k] = mul ? tb[k] : b[k];
+            }
+            mul_regs(t, A, b);
+        } else {
+            lds_sync();
+            lds_put<S, G>(abuf, A);
+            lds_sync();
+            mul_lds(t, A, mul ? tbl + mi * Ly::WORDS : abuf);
+        }
 #pragma unroll
         for (int k = 0; k < L; ++k) A[k] = active ? t[k] : A[k];
         if (mul) mi = -1;
         else if (sq > 0) --sq;
         if (sq == 0 && mi < 0 && pos >= 0) next_window();
     }
-}
-
-// A = x^e mod n in Montgomery form: sliding window where every product takes
-// its multiplier from registers, fixed window otherwise.
-template <int S, int G, int B>
-__device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
-                                             const uint32_t *ep, int elimbs, bool use_exp,
-                                             const uint32_t (&n)[S / G], uint32_t n0inv,
-                                             const uint32_t (&one)[S / G], uint32_t *lds, int w)
-{
-    if constexpr (sliding_window(B, G))
-        group_modexp_sliding<S, G, B>(A, xt, ep, elimbs, use_exp, n, n0inv, one, lds, w);
-    else
-        group_modexp_fixed<S, G, B>(A, xt, ep, elimbs, use_exp, n, n0inv, one, lds, w);
 }
 
 // A = A * R^-1 mod n (leave Montgomery form).

@@ -303,15 +303,6 @@ __device__ __forceinline__ void rmont_mul(uint32_t (&r)[S / G], const uint32_t (
     rmont_finish<S, G, B, LAZY>(r, acc, n);
 }
 
-// Value of lane K of this lane's group (G = 2 or 4: one DPP quad permute).
-template <int G, int K>
-__device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
-{
-    static_assert(G == 2 || G == 4, "quad permutes only");
-    if constexpr (G == 2) return dpp0<K == 0 ? DPP_QP_0022 : DPP_QP_1133>(v);
-    else return dpp0<K * 0x55>(v);                    // quad_perm [K, K, K, K]
-}
-
 // Blocks Q .. G-1 of a product whose multiplier b is held in the group's
 // registers like a: block Q takes limbs Q*L .. Q*L+L-1, which lane Q holds.
 template <int S, int G, int B, int Q>

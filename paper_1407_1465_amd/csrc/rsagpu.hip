@@ -33,12 +33,12 @@ static const int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
 // 2^32.  kind 0 = plain exponentiation, kind 1 = CRT half.  Two effects pull
 // against each other: more limbs per lane amortise the per-step cross-lane
 // work (broadcast of m, the limb that moves down) over 2L products and give
-// each wave more independent multiplications, while the LDS table
-// (2^w * 256 * L bytes per wave) and the registers limit the waves a CU holds.
-// For 1024-bit halves L = 18 (G = 2) at one wave per SIMD beats L = 9 (G = 4)
-// at two; for full 1024-bit exponents L = 18 at two waves per SIMD is best.
-// With 2 or 4 lanes per group the window is a sliding window over odd powers
-// (2^(w-1) LDS buffers), so w = 4 there costs the LDS of a fixed 3-bit window.
+// each wave more independent multiplications, while the LDS table (the
+// 2^(w-1) odd powers of the sliding window, plus an operand buffer where the
+// multiplier is read from LDS: S * (64 / G) words each) and the registers
+// limit the waves a CU holds.  For 1024-bit halves L = 18 (G = 2) at one
+// wave per SIMD beats L = 9 (G = 4) at two; for full 1024-bit exponents
+// L = 18 at two waves per SIMD is best.
 struct Plan {
     int B;
     int G;
@@ -52,14 +52,14 @@ struct Plan {
 static const int kKinds = 4;
 static const Plan kDefault[kKinds][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 3},
-     {29, 4, 4}, {29, 16, 3}, {29, 16, 2}},
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 3},
-     {29, 8, 3}, {29, 16, 3}, {29, 16, 2}},
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {29, 2, 4}, {29, 4, 4}, {29, 4, 3}, {29, 8, 3},
-     {29, 4, 4}, {29, 8, 3}, {29, 16, 2}},
-    {{32, 1, 4}, {32, 1, 4}, {32, 1, 3}, {32, 2, 3}, {32, 4, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 4},
-     {29, 8, 4}, {29, 16, 3}, {29, 16, 2}},
+    {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 4},
+     {29, 4, 4}, {29, 16, 4}, {29, 16, 3}},
+    {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 4},
+     {29, 8, 4}, {29, 16, 4}, {29, 16, 3}},
+    {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 4, 3}, {29, 8, 4},
+     {29, 4, 4}, {29, 8, 4}, {29, 16, 3}},
+    {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
+     {29, 8, 5}, {29, 16, 4}, {29, 16, 3}},
 };
 
 static int pack(const Plan &p) { return p.B << 16 | p.G << 8 | p.w; }

@@ -106,16 +106,18 @@ def test_ops_batch_plans_are_separate():
 
 
 def test_plan_lds_sizes():
-    """LDS per 64-lane workgroup: fixed window w = 2^w buffers of S*(64/G)
-    words; sliding window (radix 2^29, 2 or 4 lanes) = 2^(w-1) odd powers,
-    at least 4 buffers."""
+    """LDS per 64-lane workgroup for a sliding window of w bits: the 2^(w-1)
+    odd powers, plus one operand buffer where the multiplier is read from LDS
+    (all but the radix-2^29 plans with 2 or 4 lanes), at least 4 buffers of
+    S*(64/G) words."""
     from paper_1407_1465_amd import rsagpu
     cases = [
-        ((32, 1, 29, 2, 4), 8 * 36 * 32 * 4),     # sliding, 8 odd powers
-        ((32, 1, 29, 2, 3), 4 * 36 * 32 * 4),     # sliding, minimum of 4 buffers
-        ((32, 1, 29, 4, 5), 16 * 36 * 16 * 4),    # sliding, 16 odd powers
-        ((32, 1, 32, 8, 3), 8 * 32 * 8 * 4),      # fixed, radix 2^32
-        ((64, 0, 29, 8, 3), 8 * 72 * 8 * 4),      # fixed, 8 lanes per group
+        ((32, 1, 29, 2, 4), 8 * 36 * 32 * 4),     # register multipliers, 8 odd powers
+        ((32, 1, 29, 2, 3), 4 * 36 * 32 * 4),     # minimum of 4 buffers
+        ((32, 1, 29, 4, 5), 16 * 36 * 16 * 4),    # 16 odd powers
+        ((32, 1, 32, 8, 4), 9 * 32 * 8 * 4),      # LDS multipliers: 8 odd powers + operand buffer
+        ((64, 0, 29, 8, 3), 5 * 72 * 8 * 4),      # 4 odd powers + operand buffer
+        ((64, 0, 29, 8, 2), 4 * 72 * 8 * 4),      # minimum of 4 buffers
     ]
     try:
         for args, lds in cases:
