@@ -324,20 +324,16 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     ExpBits eb{ep, use_exp ? elimbs : 0, 0, 0, 0};
     int pos = (int)ebits - 1;                   // next bit to scan
     int sq = 0, mi = -1;                        // pending squarings, pending table index
-    // Takes the next window at pos: a run of zero bits (one squaring each,
-    // the run cut at the bottom of the bit buffer and at bit 0) or a window
-    // ending in a one (its length in squarings, then T[(v-1)/2]).
+    // Takes the next window at pos: a zero bit (one squaring) or a window
+    // ending in a one (its length in squarings, then T[(v-1)/2]).  (Taking
+    // whole runs of zero bits at once measured slower: the extra scanning
+    // code costs more than the calls it saves.)
     auto next_window = [&]() {
         eb.seek(pos);
-        const int off = pos - 32 * (eb.kw - 1);           // 32 .. 63
-        if (((uint32_t)(eb.bits >> off) & 1u) == 0u) {
-            const uint64_t x = eb.bits << (63 - off);     // bit pos on top
-            int run = x ? __clzll(x) : 64;                // zeros from pos down (>= 1)
-            run = run < off ? run : off;
-            run = run < pos + 1 ? run : pos + 1;
-            sq = run;
+        if (((uint32_t)(eb.bits >> (pos - 32 * (eb.kw - 1))) & 1u) == 0u) {
+            sq = 1;
             mi = -1;
-            pos -= run;
+            pos -= 1;
             return;
         }
         const int lo0 = pos - w + 1 > 0 ? pos - w + 1 : 0;

@@ -4,9 +4,7 @@ The exponentiation kernels with 2 or 4 lanes per group run a left-to-right
 sliding window per group: a two-word bit buffer refilled one word ahead, a
 leading window that initialises A from the odd-power table, then one
 Montgomery product per slot (squaring, or product with T[k] = x^(2k+1)).
-(zero bits are taken as runs, cut at the bottom of the bit buffer and at
-bit 0).  This
-replays exactly those steps on the exponent alone (A's exponent doubles
+This replays exactly those steps on the exponent alone (A's exponent doubles
 on a squaring and grows by 2k+1 on a table product) and checks that the
 schedule reaches e, stays within the table, and does the expected number of
 products.  The GPU parity tests check the kernels' results themselves.
@@ -61,11 +59,7 @@ def schedule(e, w):
         off = p - 32 * (eb.kw - 1)
         assert 32 <= off <= 63
         if ((eb.bits >> off) & 1) == 0:
-            x = (eb.bits << (63 - off)) & ((1 << 64) - 1)
-            z = 64 - x.bit_length()               # leading zeros of a 64-bit word
-            run = min(z, off, p + 1)
-            assert run >= 1
-            st.update(sq=run, mi=-1, pos=p - run)
+            st.update(sq=1, mi=-1, pos=p - 1)
             return
         lo0 = max(p - w + 1, 0)
         v = eb.field(p, lo0)
