@@ -9,7 +9,8 @@ line carries
 
   roofline:     the decryption kernel against the chip's 32x32-bit integer
                 multiply peak: algorithmic products per launch (Montgomery
-                products of the fixed-window method, 2h^2 + h each, plus the
+                products of the sliding-window schedule the plan runs,
+                counted from the actual exponents, 2h^2 + h each, plus the
                 recombination) over the kernel's mean launch time from HIP
                 events recorded on the stream it runs on;
   cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) timed on a bounded

@@ -27,7 +27,9 @@
 //     (the carry-lookahead identity carries = (A + B) ^ A ^ B).
 //
 // The multiplier b is read from LDS (group-uniform addresses, so a broadcast
-// within the group); the multiplicand a and the modulus n sit in VGPRs.
+// within the group) or, for groups of 1, 2 or 4 lanes, broadcast from the
+// group's own registers by DPP (mont_mul_regs); the multiplicand a and the
+// modulus n sit in VGPRs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -111,14 +113,6 @@ __device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
     if constexpr (G == 1) return v;
     else if constexpr (G == 2) return dpp0<K == 0 ? DPP_QP_0022 : DPP_QP_1133>(v);
     else return dpp0<K * 0x55>(v);                    // quad_perm [K, K, K, K]
-}
-
-// Value of lane `src` of this lane's group (not on hot paths).
-template <int G>
-__device__ __forceinline__ uint32_t grp_bcast(uint32_t v, int src)
-{
-    if constexpr (G == 1) return v;
-    else return (uint32_t)__shfl((int)v, src, G);
 }
 
 // Lane r receives lane (r+1) mod G of its group.  Used where the group's
@@ -401,31 +395,6 @@ __device__ __forceinline__ void grp_cond_sub(uint32_t (&x)[S / G], uint32_t top,
     const bool take = over || !borrow;
 #pragma unroll
     for (int j = 0; j < L; ++j) x[j] = take ? d[j] : x[j];
-}
-
-// x = (x + y) mod n for x, y < n.
-template <int S, int G>
-__device__ __forceinline__ void grp_add_mod(uint32_t (&x)[S / G], const uint32_t (&y)[S / G],
-                                            const uint32_t (&n)[S / G])
-{
-    const uint32_t ovf = grp_add<S, G>(x, y);
-    grp_cond_sub<S, G>(x, ovf, n);
-}
-
-// x = (x - y) mod n for x, y < n.
-template <int S, int G>
-__device__ __forceinline__ void grp_sub_mod(uint32_t (&x)[S / G], const uint32_t (&y)[S / G],
-                                            const uint32_t (&n)[S / G])
-{
-    constexpr int L = S / G;
-    uint32_t d[L];
-    const uint32_t neg = grp_sub<S, G>(d, x, y);
-    uint32_t e[L];
-#pragma unroll
-    for (int j = 0; j < L; ++j) e[j] = d[j];
-    grp_add<S, G>(e, n);
-#pragma unroll
-    for (int j = 0; j < L; ++j) x[j] = neg ? e[j] : d[j];
 }
 
 // x = 2x mod n for x < n.

@@ -1,10 +1,10 @@
 // Batched modular-exponentiation kernels for gfx950.
 //
 // A 64-lane workgroup (one wave) holds NG = 64 / G exponentiations, one per
-// lane group.  The per-wave LDS holds one operand buffer (the multiplier of
-// the next Montgomery product) and the fixed-window table T[1 .. 2^w - 1],
-// each entry one S-limb integer per group (paper, Section 3.6.4: left-to-right
-// k-ary exponentiation with a precomputed table of the powers g^1 .. g^(2^k-1)).
+// lane group.  The per-wave LDS holds the sliding window's table of odd
+// powers T[k] = x^(2k+1) (paper, Section 3.6.5, a refinement of the k-ary
+// method of Section 3.6.4) and, where the multiplier of a product is read
+// from LDS, one operand buffer; each entry is one S-limb integer per group.
 //
 // The kernels are generic over the limb radix 2^B: B = 32 uses the carry-
 // tracking arithmetic of group_bn.hpp, B < 32 the carry-free accumulation of

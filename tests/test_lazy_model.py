@@ -116,8 +116,8 @@ def rand_modulus(rng, bits):
 
 @pytest.mark.parametrize("S,G,bits", [(18, 2, 512), (36, 4, 1024), (36, 2, 1024), (28, 4, 768)])
 def test_lazy_chain_matches_python(S, G, bits):
-    """A chain of lazy products (squarings and products with a fixed-window
-    table, as in the exponentiation) stays below 2n with bounded limbs and no
+    """A chain of lazy products (squarings and products with a window table,
+    as in the exponentiation) stays below 2n with bounded limbs and no
     accumulator overflow; one canonical product at the end gives x^e mod n."""
     rng = random.Random(S * 1000 + G + bits)
     B = 29
