@@ -10,9 +10,11 @@ line carries
   roofline:     the decryption kernel against the chip's 32x32-bit integer
                 multiply peak: algorithmic products per launch (Montgomery
                 products of the sliding-window schedule the plan runs,
-                counted from the actual exponents, 2h^2 + h each, plus the
-                recombination) over the kernel's mean launch time from HIP
-                events recorded on the stream it runs on;
+                counted from the actual exponents, 2h^2 + h per product and
+                h(h+1)/2 + h^2 + h per squaring where the kernel squares
+                with one product per limb pair, plus the recombination)
+                over the kernel's mean launch time from HIP events recorded
+                on the stream it runs on;
   cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) timed on a bounded
                 sample of the same messages on the host's cores.
 
@@ -36,14 +38,15 @@ INT32_MUL_PEAK = 256 * 64 * 2.4e9
 METRIC = "2048-bit modexp/sec (CRT decrypt) on 1 GPU, %INT32-mul peak; p50/p99 latency"
 
 
-def sliding_window_montmuls(e: int, w: int) -> int:
-    """Montgomery products of the left-to-right sliding window over odd
-    powers for exponent e: the table (x^2 and 2^(w-1) - 1 products; for
-    exponents of at most 64 bits only up to the largest power used), one
-    squaring per bit below the leading window, one product per further
-    window (a window ends in a one bit and spans at most w bits)."""
+def sliding_window_counts(e: int, w: int):
+    """(squarings, table products, table size) of the left-to-right sliding
+    window over odd powers for exponent e: one squaring per bit below the
+    leading window, one product per further window (a window ends in a one
+    bit and spans at most w bits), and a table of 2^(w-1) odd powers (for
+    exponents of at most 64 bits only up to the largest power used) built
+    with x^2 and one product per further entry."""
     if e == 0:
-        return 0
+        return 0, 0, 0
     pos, sq, mul, first, used = e.bit_length() - 1, 0, 0, True, 0
     while pos >= 0:
         if not (e >> pos) & 1:
@@ -57,12 +60,44 @@ def sliding_window_montmuls(e: int, w: int) -> int:
             sq, mul = sq + pos - lo + 1, mul + 1
         first, pos = False, lo - 1
     tsize = (1 << (w - 1)) if e.bit_length() > 64 else used
+    return sq, mul, tsize
+
+
+def sliding_window_montmuls(e: int, w: int) -> int:
+    """Montgomery products (squarings included) of one exponentiation."""
+    sq, mul, tsize = sliding_window_counts(e, w)
     return sq + mul + (tsize if tsize > 1 else 0)
 
 
-def montmuls(e: int, plan) -> int:
-    """Montgomery products of one exponentiation with the plan's window."""
-    return sliding_window_montmuls(e, plan.window_bits)
+def mont_products(s: int) -> int:
+    """32x32-bit products of one Montgomery product of s 32-bit limbs:
+    s^2 for a*b, s^2 for m*n, s for the m_i."""
+    return 2 * s * s + s
+
+
+def sqr_products(s: int) -> int:
+    """32x32-bit products of one Montgomery squaring of s 32-bit limbs when
+    each pair of limbs is multiplied once: s(s+1)/2 for a^2, s^2 + s for the
+    reduction."""
+    return s * (s + 1) // 2 + s * s + s
+
+
+def symmetric_squarings(plan) -> bool:
+    """Whether the plan's kernel squares with one product per limb pair:
+    radix 2^29 with the multiplier in registers (2 or 4 lanes per
+    exponentiation) and at most 20 limbs per lane.  Its waves do so when
+    all their exponents are equal (one key, or a public exponent); the
+    count below credits every squaring at the symmetric cost, so a wave
+    that mixes exponents is charged less than it computes."""
+    return plan.radix_bits == 29 and plan.lanes_per_op in (2, 4) and 3 * plan.limbs_per_lane <= 62
+
+
+def exp_products(e: int, plan, s: int) -> int:
+    """Algorithmic 32x32-bit products of x^e mod n at s 32-bit limbs with
+    the plan's window."""
+    sq, mul, tsize = sliding_window_counts(e, plan.window_bits)
+    per_sq = sqr_products(s) if symmetric_squarings(plan) else mont_products(s)
+    return sq * per_sq + (mul + (tsize if tsize > 1 else 0)) * mont_products(s)
 
 
 def per_key_sum(key_of, fn) -> int:
@@ -73,19 +108,14 @@ def per_key_sum(key_of, fn) -> int:
                                                              keys)).items())
 
 
-def mont_products(s: int) -> int:
-    """32x32-bit products of one Montgomery product of s 32-bit limbs."""
-    return 2 * s * s + s
-
-
 def crt_products(key, plan) -> int:
+    """Two half exponentiations and Garner's product (h^2 more for m_q + h*q)."""
     h = key.limbs // 2
-    mm = montmuls(key.dp, plan) + montmuls(key.dq, plan)
-    return mm * mont_products(h) + mont_products(h) + h * h
+    return exp_products(key.dp, plan, h) + exp_products(key.dq, plan, h) + mont_products(h) + h * h
 
 
 def modexp_products(key, e: int, plan) -> int:
-    return montmuls(e, plan) * mont_products(key.limbs)
+    return exp_products(e, plan, key.limbs)
 
 
 def timed(fn, steps, warmup, torch):
@@ -144,12 +174,15 @@ def roofline(products, ms, kernel):
 
 def cpu_baseline(oracle, base, exp, mod, gpu_out, ns, unit, what):
     threads = min(16, os.cpu_count() or 1)
+    c0 = time.process_time()
     got, cwall, used = oracle.modexp_batch(base[:ns], exp[:ns], mod[:ns], nthreads=threads)
+    ccpu = time.process_time() - c0
     import numpy as np
     if not np.array_equal(got, gpu_out[:ns]):
         raise SystemExit("GPU output differs from the oracle on the CPU sample")
     return {"value": ns / cwall, "unit": unit, "cores": used, "kind": "oracle",
-            "sample": "first %d messages of the same batch, %s, %.1f s wall" % (ns, what, cwall)}
+            "sample": "first %d messages of the same batch, %s, %.1f s wall, %.1f s CPU"
+                      % (ns, what, cwall, ccpu)}
 
 
 def main():
@@ -160,7 +193,7 @@ def main():
     ap.add_argument("--workload", default="crt2048",
                     choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve"])
     ap.add_argument("--count", type=int, default=0, help="messages (0: the workload's size)")
-    ap.add_argument("--cpu-sample", type=int, default=512,
+    ap.add_argument("--cpu-sample", type=int, default=1536,
                     help="messages the CPU oracle processes for the baseline (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-mib", type=int, default=0,

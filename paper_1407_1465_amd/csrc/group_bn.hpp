@@ -213,6 +213,15 @@ __device__ __forceinline__ uint32_t grp_max(uint32_t v)
     return v;
 }
 
+// The first active lane's value of a pointer (wave-uniform from here on).
+__device__ __forceinline__ const uint32_t *first_lane_ptr(const uint32_t *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (const uint32_t *)(((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ uint32_t wave_max(uint32_t v)
 {
 #pragma unroll
@@ -338,8 +347,17 @@ __device__ __forceinline__ void lds_get(uint32_t (&x)[S / G], const uint32_t *bu
     }
 }
 
-// Orders the LDS traffic of the whole workgroup (one wave per workgroup).
-__device__ __forceinline__ void lds_sync() { __syncthreads(); }
+// Orders this wave's LDS traffic between its lanes.  Every wave works in an
+// LDS region of its own, and one wave's LDS operations are performed in the
+// order it issues them, so only the compiler has to be kept from moving
+// accesses across this point (a wavefront-scope fence emits no wait).  Data
+// exchanged between the waves of a workgroup needs __syncthreads().
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // ---- group-wide add / subtract / compare -------------------------------
 

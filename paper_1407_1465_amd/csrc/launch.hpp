@@ -12,9 +12,10 @@ namespace rsagpu {
 typedef hipError_t (*modexp_launcher)(const uint32_t *base, const uint32_t *exp, const uint32_t *mod,
                                       uint32_t *out, size_t count, int limbs, int w,
                                       unsigned long long *errs, hipStream_t stream);
+// order: the processing order of the messages (count indices) or nullptr.
 typedef hipError_t (*crt_launcher)(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
-                                   const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count, int hl,
-                                   int w, unsigned long long *errs, hipStream_t stream);
+                                   const uint32_t *dq, const uint32_t *qinv, const unsigned *order, uint32_t *out,
+                                   size_t count, int hl, int w, unsigned long long *errs, hipStream_t stream);
 
 struct KeyDev;
 struct ModConsts;
@@ -58,8 +59,8 @@ hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32
 
 template <int H, int G, int B>
 hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
-                      const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count, int hl, int w,
-                      unsigned long long *errs, hipStream_t stream);
+                      const uint32_t *dq, const uint32_t *qinv, const unsigned *order, uint32_t *out, size_t count,
+                      int hl, int w, unsigned long long *errs, hipStream_t stream);
 
 template <int S, int G, int B>
 hipError_t launch_setup(const uint32_t *const *mods, const uint32_t *const *mults, const int *words,

@@ -19,13 +19,13 @@ hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32
 
 template <int H, int G, int B>
 hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
-                      const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count, int hl, int w,
-                      unsigned long long *errs, hipStream_t stream)
+                      const uint32_t *dq, const uint32_t *qinv, const unsigned *order, uint32_t *out, size_t count,
+                      int hl, int w, unsigned long long *errs, hipStream_t stream)
 {
-    const size_t pairs = 64 / G / 2;
-    const size_t blocks = (count + pairs - 1) / pairs;
-    hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(64), lds_bytes_for(H, G, B, w), stream, c, p, q,
-                       dp, dq, qinv, out, (unsigned long long)count, hl, w, errs);
+    const size_t ng = 64 / G;                  // messages per two-wave workgroup
+    const size_t blocks = (count + ng - 1) / ng;
+    hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(128), 2 * lds_bytes_for(H, G, B, w), stream, c,
+                       p, q, dp, dq, qinv, order, out, (unsigned long long)count, hl, w, errs);
     return hipGetLastError();
 }
 
@@ -79,8 +79,8 @@ int ops_blocks_per_cu(int kind, int w)
                                                       hipStream_t);                                         \
     template hipError_t rsagpu::launch_crt<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *,    \
                                                    const uint32_t *, const uint32_t *, const uint32_t *,    \
-                                                   uint32_t *, size_t, int, int, unsigned long long *,      \
-                                                   hipStream_t);                                            \
+                                                   const unsigned *, uint32_t *, size_t, int, int,          \
+                                                   unsigned long long *, hipStream_t);                      \
     template hipError_t rsagpu::launch_setup<S_, G_, B_>(const uint32_t *const *, const uint32_t *const *,  \
                                                          const int *, rsagpu::ModConsts *, int,             \
                                                          hipStream_t);                                      \

@@ -58,6 +58,14 @@ struct Arith {
     {
         rmont_mul_regs<S, G, B, true>(r, a, b, n, n0inv);
     }
+    // Lazy square with a in registers; symmetric (rmont_sqr_regs) where kSqr.
+    static constexpr bool kSqr = (G == 2 || G == 4) && rsqr_fits<B, L>();
+    static __device__ __forceinline__ void sqr_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                         const uint32_t (&n)[L], uint32_t n0inv)
+    {
+        if constexpr (kSqr) rmont_sqr_regs<S, G, B, true>(r, a, n, n0inv);
+        else rmont_mul_regs<S, G, B, true>(r, a, a, n, n0inv);
+    }
     template <typename Sink>
     static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
                                                     const uint32_t (&a)[L], const uint32_t *b, Sink sink)
@@ -113,6 +121,12 @@ struct Arith<S, G, 32> {
                                                               uint32_t n0inv)
     {
         rsagpu::mont_mul_regs<S, G>(r, a, b, n, n0inv);
+    }
+    static constexpr bool kSqr = false;
+    static __device__ __forceinline__ void sqr_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                         const uint32_t (&n)[L], uint32_t n0inv)
+    {
+        rsagpu::mont_mul_regs<S, G>(r, a, a, n, n0inv);
     }
     template <typename Sink>
     static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
@@ -285,8 +299,13 @@ struct ExpBits {
 // from registers (DPP broadcast; the table starts at the LDS base); otherwise
 // A is staged through the operand buffer at the LDS base (the table follows
 // it) and each group's product reads its own multiplier there or in its
-// table entry.  Every product is lazy (A and the table stay below 2n in
-// redundant limbs); the caller's from_mont makes the result canonical.
+// table entry.  Where squarings can be symmetric (Arith::kSqr) and every
+// live group of the wave has the same exponent words (one key's exponent,
+// or a public exponent), the wave instead follows one schedule: its
+// squarings multiply each pair of limbs once (rmont_sqr_regs) and its table
+// products read one entry for all groups.  Every product is lazy (A and the
+// table stay below 2n in redundant limbs); the caller's from_mont makes the
+// result canonical.
 template <int S, int G, int B>
 __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
                                                      const uint32_t *ep, int elimbs, bool use_exp,
@@ -308,18 +327,25 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
         Ar::mont_mul_lazy(r, a, bl, n, n0inv);
     };
 
-    // this group's exponent length (its lanes scan slices of the words)
+    // this group's exponent length (its lanes scan slices of the words) and,
+    // where squarings can be symmetric, whether every live group of the wave
+    // has group 0's exponent: then the whole wave follows one schedule
+    constexpr bool UNI = REG && Ar::kSqr;
+    const int el = use_exp ? elimbs : 0;
     uint32_t ebits = 0;
-    if (use_exp) {
-        const int per = (elimbs + G - 1) / G;
+    bool same = true;
+    {
+        const int per = ((int)wave_max((uint32_t)el) + G - 1) / G;
         const int r = grp_lane<G>();
         for (int k = 0; k < per; ++k) {
             const int li = r * per + k;
-            const uint32_t v = li < elimbs ? ep[li] : 0u;
+            const uint32_t v = li < el ? ep[li] : 0u;
             if (v) ebits = (uint32_t)(32 * li + 32 - __clz(v));
+            if constexpr (UNI) same = same && (!use_exp || v == (uint32_t)__shfl((int)v, r));
         }
     }
     ebits = grp_max<G>(ebits);
+    const bool uniform = UNI && __ballot(!same) == 0;
 
     ExpBits eb{ep, use_exp ? elimbs : 0, 0, 0, 0};
     int pos = (int)ebits - 1;                   // next bit to scan
@@ -388,6 +414,33 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
             }
         }
         lds_sync();
+    }
+
+    if constexpr (UNI) {
+        if (uniform) {
+            // One schedule for the wave, group 0's (all live groups share its
+            // exponent; the others' results are not used): squarings are
+            // symmetric and no multiplier is selected per group.
+            eb = ExpBits{first_lane_ptr(ep), __builtin_amdgcn_readfirstlane(el), 0, 0, 0};
+            pos = __builtin_amdgcn_readfirstlane((int)ebits) - 1;
+#pragma unroll
+            for (int k = 0; k < L; ++k) A[k] = one[k];
+            if (pos < 0) return;
+            eb.start(pos);
+            next_window();                      // the leading window sets A
+            lds_get<S, G>(A, tbl + __builtin_amdgcn_readfirstlane(mi) * Ly::WORDS, g);
+            while (__builtin_amdgcn_readfirstlane(pos) >= 0) {
+                next_window();
+                const int nsq = __builtin_amdgcn_readfirstlane(sq), ui = __builtin_amdgcn_readfirstlane(mi);
+                for (int q = 0; q < nsq; ++q) Ar::sqr_regs_lazy(A, A, n, n0inv);
+                if (ui >= 0) {
+                    uint32_t tb[L];
+                    lds_get<S, G>(tb, tbl + ui * Ly::WORDS, g);
+                    mul_regs(A, A, tb);
+                }
+            }
+            return;
+        }
     }
 
 #pragma unroll
@@ -484,51 +537,52 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_modexp(const uint3
 
 // ---- CRT decryption ------------------------------------------------------
 //
-// Groups come in pairs: even group = the half modulo p, odd group = modulo q
-// of the same message.  p, q, dp, dq, qinv have hl 32-bit words, c and the
-// result 2*hl; H limbs of radix 2^B hold a half (B*H >= 32*hl).
+// A workgroup of two waves takes NG = 64 / G messages: wave 0 the halves
+// modulo p, wave 1 the halves modulo q, one message per lane group, so a
+// wave's exponents are all dp (or all dq) and, when its messages share a key,
+// equal (group_modexp then runs one schedule with symmetric squarings).
+// Message i of the workgroup is order[blockIdx.x * NG + i] (the identity
+// without an order).  p, q, dp, dq, qinv have hl 32-bit words, c and the
+// result 2*hl; H limbs of radix 2^B hold a half (B*H >= 32*hl).  Each wave
+// works in its own LDS region; m_q and its validity reach wave 0 through
+// wave 1's region, and wave 0 recombines (Garner) and stores.
 template <int H, int G, int B>
-__global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, const uint32_t *__restrict__ p,
-                                            const uint32_t *__restrict__ q, const uint32_t *__restrict__ dp,
-                                            const uint32_t *__restrict__ dq, const uint32_t *__restrict__ qinv,
-                                            uint32_t *out, unsigned long long count, int hl, int w,
-                                            unsigned long long *errs)
+__global__ __launch_bounds__(128) void k_crt(const uint32_t *__restrict__ c, const uint32_t *__restrict__ p,
+                                             const uint32_t *__restrict__ q, const uint32_t *__restrict__ dp,
+                                             const uint32_t *__restrict__ dq, const uint32_t *__restrict__ qinv,
+                                             const unsigned *__restrict__ order, uint32_t *out,
+                                             unsigned long long count, int hl, int w, unsigned long long *errs)
 {
     using Ar = Arith<H, G, B>;
     using Ly = Layout<H, G>;
     constexpr int L = H / G, NG = 64 / G;
-    static_assert(NG >= 2, "a wave holds at least one pair of groups");
-    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
+    const int half = (int)(threadIdx.x >> 6);
+    const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
+    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + half * region;
+    uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + region;     // wave 1's region
     const int g = grp_index<G>(), r = grp_lane<G>();
-    const int half = g & 1;
-    const unsigned long long msg = (unsigned long long)blockIdx.x * (NG / 2) + (g >> 1);
-    const bool live = msg < count;
+    const unsigned long long slot = (unsigned long long)blockIdx.x * NG + g;
+    const bool live = slot < count;
+    const unsigned long long msg = live ? (order ? (unsigned long long)order[slot] : slot) : 0ull;
     const size_t hoff = live ? (size_t)msg * (size_t)hl : 0;
     const size_t foff = 2 * hoff;
     const int full = 2 * hl;
 
-    uint32_t n[L], clo[L], chi[L], other[L];
+    uint32_t n[L], clo[L], chi[L];
     Ar::load(n, (half ? q : p) + hoff, hl, 0, live);
-    Ar::load(other, (half ? p : q) + hoff, hl, 0, live);     // p-groups need q
     Ar::load(clo, c + foff, full, 0, live);                   // c mod R
     Ar::load(chi, c + foff, full, B * H, live);               // c div R
     const uint32_t n0 = grp_bcast0<G>(n[0]);
     const uint32_t bl = Ar::bitlen(n);
     bool valid = live && (n0 & 1u) && bl > 1;
-    {   // p > q, evaluated by every group and used by the p-groups
-        uint32_t d[L];
+    if (!half) {   // p > q
+        uint32_t other[L], d[L];
+        Ar::load(other, q + hoff, hl, 0, live);
         const uint32_t lt = Ar::sub(d, n, other);
         bool nz = false;
 #pragma unroll
         for (int k = 0; k < L; ++k) nz = nz || d[k] != 0u;
-        const bool gt = !lt && grp_any<G>(nz);
-        valid = valid && (half || gt);
-    }
-    {   // a pair is valid only if both of its groups are
-        const unsigned pbase = (lane_id() / (2 * G)) * (2 * G);
-        const uint64_t pmask = (2 * G == 64) ? ~0ull : (((1ull << (2 * G)) - 1) << pbase);
-        const bool bad = (__ballot(!valid) & pmask) != 0;
-        valid = valid && !bad;
+        valid = valid && !lt && grp_any<G>(nz);
     }
     const uint32_t n0inv = Ar::n0inv(n0 | 1u);
 
@@ -549,13 +603,20 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
     group_modexp<H, G, B>(A, xt, (half ? dq : dp) + hoff, hl, valid, n, n0inv, one, lds, w);
     from_mont<H, G, B>(A, lds, n, n0inv);
 
-    // Garner: h = qinv * (m_p - m_q) mod p, m = m_q + h * q  (on the p-group)
+    // wave 1 hands m_q and its validity to wave 0
+    if (half) {
+        lds_sync();
+        lds_put<H, G>(qlds, A);
+        if (r == 0) qlds[Ly::WORDS + g] = valid ? 1u : 0u;
+    }
+    __syncthreads();
+    if (half) return;
+
+    // Garner: h = qinv * (m_p - m_q) mod p, m = m_q + h * q
     uint32_t mq[L], qv[L], hh[L];
-    lds_sync();
-    lds_put<H, G>(lds, A);
-    lds_sync();
-    lds_get<H, G>(mq, lds, g ^ 1);
-    {   // delta = m_p - m_q mod p
+    lds_get<H, G>(mq, qlds, g);
+    valid = valid && qlds[Ly::WORDS + g] != 0u;
+    {   // delta = m_p - m_q mod p  (m_q < q < p)
         uint32_t d[L];
         const uint32_t neg = Ar::sub(d, A, mq);
         uint32_t e[L];
@@ -565,7 +626,7 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
 #pragma unroll
         for (int k = 0; k < L; ++k) A[k] = neg ? e[k] : d[k];
     }
-    Ar::load(qv, qinv + hoff, hl, 0, live && !half);
+    Ar::load(qv, qinv + hoff, hl, 0, live);
     mont_mul_reg<H, G, B>(qv, qv, r2, lds, n, n0inv);         // qinv * R mod p
     mont_mul_reg<H, G, B>(hh, A, qv, lds, n, n0inv);          // delta * qinv mod p
     lds_sync();
@@ -576,13 +637,13 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
     auto sink = [&](int i, uint32_t v) {
         if (r == 0) stage[i] = v;
     };
-    uint32_t high[L];
-    Ar::load(other, (half ? p : q) + hoff, hl, 0, live);     // reloaded: not kept live across the loop
-    Ar::mul_wide(high, mq, other, lds, sink);
+    uint32_t high[L], qn[L];
+    Ar::load(qn, q + hoff, hl, 0, live);
+    Ar::mul_wide(high, mq, qn, lds, sink);
 #pragma unroll
     for (int k = 0; k < L; ++k) stage[H + r * L + k] = high[k];
     lds_sync();
-    if (live && !half) {
+    if (live) {
         uint32_t *o = out + foff;
         if constexpr (B == 32) {
             for (int wd = r; wd < full; wd += G) o[wd] = valid ? stage[wd] : 0u;
@@ -590,7 +651,7 @@ __global__ __launch_bounds__(64) void k_crt(const uint32_t *__restrict__ c, cons
             for (int wd = r; wd < full; wd += G) o[wd] = valid ? rword<B>(stage, 2 * H, wd) : 0u;
         }
     }
-    if (live && !half && r == 0 && !valid) atomicAdd(errs, 1ull);
+    if (live && r == 0 && !valid) atomicAdd(errs, 1ull);
 }
 
 }  // namespace rsagpu

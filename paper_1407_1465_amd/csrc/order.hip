@@ -1,0 +1,130 @@
+// Grouping of a plain CRT batch by key: a processing order in which messages
+// under the same key follow each other, so that the waves of the CRT kernel
+// mostly hold one key's halves (one exponent per wave: one schedule, symmetric
+// squarings).  A counting sort of the messages by a hash of their key words
+// (p, dp, dq) into kBuckets = 2^16 buckets; distinct keys that share a
+// bucket only share waves, which then take the per-group schedule.  The order changes
+// which messages share a wave, never a result.
+#include "registry.hpp"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsagpu {
+
+static const int kBucketBits = 16;
+static const int kBuckets = 1 << kBucketBits;
+
+__device__ __forceinline__ uint32_t key_bucket(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t i,
+                                               int hl)
+{
+    const size_t o = i * (size_t)hl;
+    const uint32_t p1 = hl > 1 ? p[o + 1] : 0u;
+    uint32_t h = p[o] * 0x9E3779B1u;
+    h ^= (p1 + 0x7F4A7C15u) * 0x85EBCA77u;
+    h = (h << 13 | h >> 19) ^ dp[o] * 0xC2B2AE3Du;
+    h = (h << 11 | h >> 21) ^ dq[o] * 0x27D4EB2Fu;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return h >> (32 - kBucketBits);
+}
+
+__global__ void k_order_clear(unsigned *cnt)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < kBuckets) cnt[t] = 0u;          // a fill kernel, not a memset: safe to capture in a graph
+}
+
+__global__ void k_order_count(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, unsigned long long count,
+                              int hl, unsigned *cnt)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    atomicAdd(&cnt[key_bucket(p, dp, dq, i, hl)], 1u);
+}
+
+// Exclusive prefix sum of the bucket counts, in place (one workgroup of
+// 1024 threads, kBuckets / 1024 buckets per thread).
+__global__ __launch_bounds__(1024) void k_order_scan(unsigned *cnt)
+{
+    constexpr int PER = kBuckets / 1024;
+    __shared__ unsigned part[1024];
+    const int t = threadIdx.x;
+    unsigned v[PER], s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = cnt[t * PER + k];
+        s += v[k];
+    }
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {       // inclusive scan of the partial sums
+        const unsigned add = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    unsigned run = part[t] - s;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        cnt[t * PER + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ void k_order_place(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, unsigned long long count,
+                              int hl, unsigned *cursor, unsigned *order)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const unsigned at = atomicAdd(&cursor[key_bucket(p, dp, dq, i, hl)], 1u);
+    order[at] = (unsigned)i;
+}
+
+// Stream-ordered scratch from the device's default pool, kept cached by the
+// pool between calls.
+static void keep_pool_memory()
+{
+    static bool done[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    done[dev] = true;
+}
+
+unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
+                    hipStream_t stream)
+{
+    if (count > 0xFFFFFFFFull) return nullptr;
+    keep_pool_memory();
+    void *mem = nullptr;
+    if (hipMallocAsync(&mem, (count + kBuckets) * sizeof(unsigned), stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    unsigned *cnt = static_cast<unsigned *>(mem), *order = cnt + kBuckets;
+    const unsigned blocks = (unsigned)((count + 255) / 256);
+    hipLaunchKernelGGL(k_order_clear, dim3(kBuckets / 256), dim3(256), 0, stream, cnt);
+    hipLaunchKernelGGL(k_order_count, dim3(blocks), dim3(256), 0, stream, p, dp, dq, (unsigned long long)count, hl,
+                       cnt);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, stream, cnt);
+    hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(256), 0, stream, p, dp, dq, (unsigned long long)count, hl,
+                       cnt, order);
+    if (hipGetLastError() != hipSuccess) {
+        (void)hipFreeAsync(mem, stream);
+        return nullptr;
+    }
+    return order;
+}
+
+void free_key_order(unsigned *order, hipStream_t stream)
+{
+    if (order) (void)hipFreeAsync(order - kBuckets, stream);
+}
+
+}  // namespace rsagpu

@@ -221,6 +221,24 @@ __device__ __forceinline__ void racc_lazy(uint32_t (&w)[S / G], const uint64_t (
 
 // ---- Montgomery product, radix 2^B -----------------------------------------
 
+// Reduction half of CIOS step k of a block: m from the group's lowest
+// position (lane 0, register k), m * n into the rotating positions, the
+// lowest register's carry into the next and its low B bits one lane down.
+template <int S, int G, int B>
+__device__ __forceinline__ void rcios_reduce(uint64_t (&acc)[S / G], int k, const uint32_t (&n)[S / G],
+                                             uint32_t n0inv)
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+    const int p0 = k % L, p1 = (k + 1) % L;
+    const uint32_t m = grp_bcast0<G>(((uint32_t)acc[p0] * n0inv) & M);
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)m * n[j];
+    acc[p1] += acc[p0] >> B;
+    // the group's lane 0 holds zero in its low B bits here
+    acc[p0] = grp_rot_down<G>((uint32_t)acc[p0] & M);
+}
+
 // The L CIOS steps of one block: multiplier limbs bv[0 .. L) (already
 // broadcast to the group), accumulator positions rotating through acc.
 template <int S, int G, int B>
@@ -229,18 +247,11 @@ __device__ __forceinline__ void rcios_block(uint64_t (&acc)[S / G], const uint32
                                             uint32_t n0inv)
 {
     constexpr int L = S / G;
-    constexpr uint32_t M = Radix<B>::MASK;
 #pragma unroll
     for (int k = 0; k < L; ++k) {
 #pragma unroll
         for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * bv[k];
-        const int p0 = k % L, p1 = (k + 1) % L;
-        const uint32_t m = grp_bcast0<G>(((uint32_t)acc[p0] * n0inv) & M);
-#pragma unroll
-        for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)m * n[j];
-        acc[p1] += acc[p0] >> B;
-        // the group's lane 0 holds zero in its low B bits here
-        acc[p0] = grp_rot_down<G>((uint32_t)acc[p0] & M);
+        rcios_reduce<S, G, B>(acc, k, n, n0inv);
     }
 }
 
@@ -336,6 +347,69 @@ __device__ __forceinline__ void rmont_mul_regs(uint32_t (&r)[S / G], const uint3
 #pragma unroll
     for (int j = 0; j < L; ++j) acc[j] = 0;
     RRegBlocks<S, G, B, 0>::run(acc, a, b, n, n0inv);
+    rmont_finish<S, G, B, LAZY>(r, acc, n);
+}
+
+// Limbs per lane for which a squaring (rmont_sqr_regs) cannot overflow an
+// accumulator: its products carry a factor 2, so a register gathers at most
+// L products below 2^(2B+1) * (1 + 2^-20) and L below 2^(2B) * (1 + 2^-20)
+// between two drains, plus the carry and the limb.
+template <int B, int L>
+constexpr bool rsqr_fits()
+{
+    return L >= 1 && 3 * L <= (1 << (64 - 2 * B)) - 2;
+}
+
+// Block Q of a Montgomery squaring: steps Q*L .. Q*L+L-1 take the group's
+// own limbs of lane Q as multipliers.  A square needs each unordered pair of
+// limbs once, doubled, and each limb squared once.  Lane r, register j, step
+// k of block Q multiplies limbs Q*L+k and r*L+j; the pair with the other
+// order of offsets (register k, step j of block r) is the same unordered
+// pair, so only registers j >= k run: j > k with the doubled multiplier for
+// every lane, and j == k per lane -- the square of the lane's own limb in
+// lane Q, the doubled pair in lanes above Q, nothing in lanes below Q (they
+// take that pair in their own block).  Every column still receives all its
+// terms no later than its drain, so m and the result are those of the
+// general product rcios_block computes with b = a; a2 holds 2a.
+template <int S, int G, int B, int Q>
+struct RSqrBlocks {
+    static __device__ __forceinline__ void run(uint64_t (&acc)[S / G], const uint32_t (&a)[S / G],
+                                               const uint32_t (&a2)[S / G], const uint32_t (&n)[S / G],
+                                               uint32_t n0inv)
+    {
+        if constexpr (Q < G) {
+            constexpr int L = S / G;
+            const int r = grp_lane<G>();
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const uint32_t b2 = grp_bcast_lane<G, Q>(a2[k]);
+                const uint32_t bd = r > Q ? b2 : (r == Q ? a[k] : 0u);
+                acc[(2 * k) % L] += (uint64_t)a[k] * bd;
+#pragma unroll
+                for (int j = k + 1; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * b2;
+                rcios_reduce<S, G, B>(acc, k, n, n0inv);
+            }
+            RSqrBlocks<S, G, B, Q + 1>::run(acc, a, a2, n, n0inv);
+        }
+    }
+};
+
+// r = a * a * 2^(-B*S) mod n with a in the group's registers (G = 2 or 4):
+// S * (L + 1) / 2 products per lane for the square instead of S * L.  Same
+// bounds and LAZY meaning as rmont_mul; r may alias a.
+template <int S, int G, int B, bool LAZY>
+__device__ __forceinline__ void rmont_sqr_regs(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
+                                               const uint32_t (&n)[S / G], uint32_t n0inv)
+{
+    constexpr int L = S / G;
+    static_assert(rsqr_fits<B, L>(), "limbs per lane too large for a squaring in this radix");
+    uint32_t a2[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) a2[k] = a[k] << 1;
+    uint64_t acc[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[j] = 0;
+    RSqrBlocks<S, G, B, 0>::run(acc, a, a2, n, n0inv);
     rmont_finish<S, G, B, LAZY>(r, acc, n);
 }
 

@@ -35,6 +35,14 @@ struct Resolved {
 };
 bool resolve(int limbs, int kind, Resolved *r);
 
+// Processing order of a plain CRT batch that puts messages under the same key
+// next to each other (device array of count indices in stream-ordered
+// scratch), or nullptr to keep the given order; free_key_order releases it
+// after the work that reads it has been queued on the same stream.
+unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
+                    hipStream_t stream);
+void free_key_order(unsigned *order, hipStream_t stream);
+
 // Per-device data-error counter (allocated once per device).
 int device_state(unsigned long long **errs);
 int status_of(hipError_t e);

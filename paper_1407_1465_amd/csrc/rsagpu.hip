@@ -181,12 +181,16 @@ extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const
     if (!c || !p || !q || !dp || !dq || !qinv || !out) return RSA_EINVAL;
     Resolved r;
     if (!resolve(limbs / 2, 1, &r)) return RSA_ELIMBS;
-    const size_t pairs = 32 / r.inst->G;
-    if ((count + pairs - 1) / pairs > 0x7FFFFFFFull) return RSA_EINVAL;
+    const size_t ng = 64 / r.inst->G;
+    if ((count + ng - 1) / ng > 0x7FFFFFFFull) return RSA_EINVAL;
     unsigned long long *errs = nullptr;
     const int st = device_state(&errs);
     if (st != RSA_OK) return st;
-    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, out, count, limbs / 2, r.w, errs, stream));
+    // more than one workgroup: process the messages grouped by key
+    unsigned *order = count > ng ? key_order(p, dp, dq, count, limbs / 2, stream) : nullptr;
+    const int rc = status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, count, limbs / 2, r.w, errs, stream));
+    free_key_order(order, stream);
+    return rc;
 }
 
 extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)

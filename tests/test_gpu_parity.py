@@ -178,6 +178,36 @@ def test_crt_rejects_p_not_greater_than_q():
     assert rsagpu.device_errors() == 1
 
 
+@pytest.mark.parametrize("bits", [256, 2048])
+def test_crt_grouped_by_key_with_data_errors(bits):
+    """Several workgroups of messages under a few keys in random order (the
+    launch regroups them by key, so waves hold one key's halves, or several
+    keys' where groups meet) with invalid elements scattered through them:
+    every valid element equals the oracle, every invalid one is 0 and
+    counted once."""
+    keys = W.make_keys(bits, 91 + bits, 3)
+    L = keys[0].limbs
+    h = L // 2
+    count = 197
+    rng = np.random.default_rng(bits)
+    key_of = rng.integers(0, 3, count)
+    r = random.Random(bits + 1)
+    C = W.ints_to_limbs([r.randrange(keys[k].n) for k in key_of], L)
+    p, q, dp, dq, qi = crt_operands(keys, key_of, L)
+    bad_swap, bad_even = 7, 140
+    k = keys[key_of[bad_swap]]
+    p[bad_swap], q[bad_swap] = W.ints_to_limbs([k.q], h)[0], W.ints_to_limbs([k.p], h)[0]
+    k = keys[key_of[bad_even]]
+    q[bad_even] = W.ints_to_limbs([k.q + 1], h)[0]
+    out = host(rsagpu.decrypt_crt(dev(C), dev(p), dev(q), dev(dp), dev(dq), dev(qi)))
+    want = oracle_modexp(C, full_operands(keys, key_of, L, "d"), full_operands(keys, key_of, L, "n"))
+    want[bad_swap] = 0
+    want[bad_even] = 0
+    wrong = np.nonzero((out != want).any(axis=1))[0]
+    assert wrong.size == 0, "%d mismatches, first at %d" % (wrong.size, wrong[0])
+    assert rsagpu.device_errors() == 2
+
+
 def test_workload_rsa2048_crt_sampled_and_roundtrip():
     """64 keys of 2048 bits, 16384 messages round-robin: CRT decryption of the
     whole batch sampled against the oracle, plus the encrypt/decrypt round trip."""

@@ -72,6 +72,36 @@ def test_instance_modexp(B, S, G, plan_guard):
     assert rsagpu.device_errors() == 0
 
 
+@pytest.mark.parametrize("B,S,G", [i for i in INSTANCES if i[2] <= 4])
+def test_instance_modexp_shared_exponent(B, S, G, plan_guard):
+    """Waves whose groups all carry the same exponent words (one key's
+    exponent, a public exponent) run one schedule for the whole wave with
+    symmetric squarings; a wave with one differing exponent, and the ragged
+    last wave, must give the same results as the per-group schedule."""
+    cls = width_class(B, S)
+    rsagpu.set_plan(cls, 0, B, G, window_for(B, S, G))
+    plan_guard.append((cls, 0))
+    rng = random.Random(B * 7 + S * 3 + G)
+    limbs, bits, ng = cls, 32 * cls, 64 // G
+    count = 2 * ng + 3
+    mods = [rng.getrandbits(bits) | (1 << (bits - 1)) | 1 for _ in range(count)]
+    mods[4] = (1 << bits) - 1
+    bases = [rng.getrandbits(bits) for _ in range(count)]
+    e1 = rng.getrandbits(bits) | (1 << (bits - 1))
+    exps = [e1] * ng + [e1] * ng + [65537] * 3
+    exps[ng + 5] = rng.getrandbits(bits)           # breaks the second wave's sharing
+    cases = [(bases, exps, mods)]
+    for e in (0, 1, 2, 3, 1 << (bits - 1), (1 << bits) - 1, 65537):
+        cases.append((bases[:ng + 1], [e] * (ng + 1), mods[:ng + 1]))
+    for bs, es, ms in cases:
+        Bv, Ev, Mv = (W.ints_to_limbs(v, limbs) for v in (bs, es, ms))
+        out = host(rsagpu.modexp(dev(Bv), dev(Ev), dev(Mv)))
+        want = oracle_modexp(Bv, Ev, Mv)
+        bad = np.nonzero((out != want).any(axis=1))[0]
+        assert bad.size == 0, "B=%d S=%d G=%d e[0]=%#x: %d bad, first %d" % (B, S, G, es[0], bad.size, bad[0])
+    assert rsagpu.device_errors() == 0
+
+
 @pytest.mark.parametrize("B,S,G", [i for i in INSTANCES if 64 // i[2] >= 2])
 def test_instance_crt(B, S, G, plan_guard):
     cls = width_class(B, S)

@@ -110,6 +110,43 @@ class Model:
         return acc
 
 
+def sqr_loop(md, a, n):
+    """The symmetric squaring's S steps (rmont_sqr_regs): step k of block q
+    runs registers j >= k only; j > k multiply by 2a[qL+k] in every lane,
+    j == k squares lane q's own limb, doubles the pair in lanes above q and
+    adds nothing in lanes below q.  Returns (accumulators, multiplier slots
+    run per lane)."""
+    S, G, L, B, M = md.S, md.G, md.L, md.B, md.M
+    ninv = n0inv_of(n[0], B)
+    acc = [[0] * L for _ in range(G)]
+    slots = 0
+    for q in range(G):
+        for k in range(L):
+            b = a[q * L + k]
+            for j in range(k, L):
+                slots += 1
+                for g in range(G):
+                    if j > k or g > q:
+                        f = 2 * b
+                    elif g == q:
+                        f = a[g * L + j]
+                    else:
+                        f = 0
+                    md._add(acc, g, (j + k) % L, a[g * L + j] * f)
+            p0, p1 = k % L, (k + 1) % L
+            m = (((acc[0][p0] & 0xFFFFFFFF) * ninv) & 0xFFFFFFFF) & M
+            for g in range(G):
+                for j in range(L):
+                    md._add(acc, g, (j + k) % L, m * n[g * L + j])
+            for g in range(G):
+                md._add(acc, g, p1, acc[g][p0] >> B)
+            low = [acc[g][p0] & M for g in range(G)]
+            assert low[0] == 0, "lowest position not cleared by m*n"
+            for g in range(G):
+                acc[g][p0] = low[g + 1] if g + 1 < G else low[0]
+    return acc, slots
+
+
 def rand_modulus(rng, bits):
     return rng.getrandbits(bits) | (1 << (bits - 1)) | (1 << (bits - 2)) | 1
 
@@ -186,3 +223,45 @@ def test_lazy_output_bound_is_tight_enough():
         assert value(r, B) % n == value(a, B) * value(b, B) * pow(R, -1, n) % n
         assert value(r, B) < 2 * n
         assert max(r) < (1 << B) + (1 << 6)
+
+
+SQR_SHAPES = [(18, 2), (28, 4), (36, 2), (36, 4), (56, 4), (72, 4)]
+
+
+@pytest.mark.parametrize("S,G", SQR_SHAPES)
+def test_symmetric_square_equals_general_product(S, G):
+    """Each unordered pair of limbs once, doubled: the same m at every step
+    (every column is complete at its drain), so the same value as the
+    general product with b = a, with S*(L+1)/2 multiplier slots per lane
+    instead of S*L, and the same lazy output bounds."""
+    B = 29
+    rng = random.Random(S * 7 + G)
+    md = Model(S, G, B)
+    L = S // G
+    R = 1 << (B * S)
+    for _ in range(4):
+        n = rand_modulus(rng, B * S - 12)
+        nl = to_limbs(n, S, B)
+        a = to_limbs(2 * n - 1 - rng.randrange(1 << 20), S, B)
+        a[1] += 1 << 6          # a redundant limb: same value, limb above 2^B
+        a[2] -= 1
+        acc, slots = sqr_loop(md, a, nl)
+        assert slots == S * (L + 1) // 2
+        w = md._lazy(acc)
+        ref = md._lazy(md.product_loop(a, a, nl))
+        assert value(w, B) == value(ref, B)
+        assert value(w, B) % n == value(a, B) ** 2 * pow(R, -1, n) % n
+        assert value(w, B) < 2 * n and max(w) < (1 << B) + (1 << 6)
+
+
+@pytest.mark.parametrize("S,G", SQR_SHAPES)
+def test_symmetric_square_accumulator_bound(S, G):
+    """Doubled products with the largest redundant limbs: no accumulator
+    reaches 2^64 for the limbs per lane the kernels square with."""
+    B = 29
+    md = Model(S, G, B)
+    big = (1 << B) + (1 << (64 - 2 * B)) - 1
+    sqr_loop(md, [big] * S, [(1 << B) - 1] * S)
+    assert (1 << 61) < md.max_acc < (1 << 64)
+    # the kernel's static bound (rsqr_fits) admits these shapes
+    assert 3 * (S // G) <= (1 << (64 - 2 * B)) - 2
