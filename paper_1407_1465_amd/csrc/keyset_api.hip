@@ -15,42 +15,84 @@ namespace rsagpu {
 static_assert(sizeof(OpDesc) == sizeof(rsa_op), "rsa_op layout");
 
 static const int kMaxBuckets = 32;            // 2 kinds x width classes
-static const size_t kWsHeader = 2 * kMaxBuckets * sizeof(unsigned);
+static const int kKeySlots = 256;             // key ids per bucket ordered apart (id mod 256)
+// workspace header: per bucket its size and claim counter, then per bucket
+// and key slot a count that becomes a list cursor
+static const size_t kWsHeader = (2 * kMaxBuckets + (size_t)kMaxBuckets * kKeySlots) * sizeof(unsigned);
 
 // ---- bucketing kernels -------------------------------------------------------
+//
+// Operations go into buckets of one (width class of the key, kind), each
+// list ordered by key id (a counting sort over id mod kKeySlots), so that
+// a bucket kernel's chunks hold one key's operations.  Invalid operations
+// (kind, key id, or an input/output range outside its pool) are counted as
+// data errors and dropped.
 
 __global__ void k_bucket_clear(unsigned *hdr)
 {
-    const int t = threadIdx.x;
-    if (t < 2 * kMaxBuckets) hdr[t] = 0u;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2 * kMaxBuckets + (size_t)kMaxBuckets * kKeySlots) hdr[t] = 0u;
 }
 
-// Sorts operations into buckets (width class of the key, kind).  Invalid
-// operations (kind, key id, or an input/output range outside its pool) are
-// counted as data errors and dropped.
-__global__ void k_bucket_fill(const OpDesc *__restrict__ ops, unsigned long long nops,
-                              const KeyDev *__restrict__ keys, int nkeys, unsigned long long in_words,
-                              unsigned long long out_words, unsigned *counts, unsigned *lists,
-                              unsigned long long cap, unsigned long long *errs)
+// Bucket of an operation, or -1 if it is invalid.
+__device__ __forceinline__ int op_bucket(const OpDesc &op, const KeyDev *keys, int nkeys,
+                                         unsigned long long in_words, unsigned long long out_words)
+{
+    if (op.kind > 1u || op.key_id < 0 || op.key_id >= nkeys) return -1;
+    const KeyDev &k = keys[op.key_id];
+    const unsigned long long wds = (unsigned long long)k.words;
+    const bool ok = op.in_off <= in_words && wds <= in_words - op.in_off && op.out_off <= out_words &&
+                    wds <= out_words - op.out_off;
+    return ok ? k.cls * 2 + (int)op.kind : -1;
+}
+
+__global__ void k_bucket_count(const OpDesc *__restrict__ ops, unsigned long long nops,
+                               const KeyDev *__restrict__ keys, int nkeys, unsigned long long in_words,
+                               unsigned long long out_words, unsigned *slots, unsigned long long *errs)
 {
     const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nops) return;
     const OpDesc op = ops[i];
-    bool ok = op.kind <= 1u && op.key_id >= 0 && op.key_id < nkeys;
-    int b = 0;
-    if (ok) {
-        const KeyDev &k = keys[op.key_id];
-        const unsigned long long wds = (unsigned long long)k.words;
-        ok = op.in_off <= in_words && wds <= in_words - op.in_off && op.out_off <= out_words &&
-             wds <= out_words - op.out_off;
-        b = k.cls * 2 + (int)op.kind;
-    }
-    if (!ok) {
+    const int b = op_bucket(op, keys, nkeys, in_words, out_words);
+    if (b < 0) {
         atomicAdd(errs, 1ull);
         return;
     }
-    const unsigned slot = atomicAdd(&counts[b], 1u);
-    lists[(unsigned long long)b * cap + slot] = (unsigned)i;
+    atomicAdd(&slots[b * kKeySlots + (op.key_id % kKeySlots)], 1u);
+}
+
+// One workgroup per bucket: exclusive prefix sum of its key-slot counts (in
+// place: they become the list cursors) and the bucket's size.
+__global__ __launch_bounds__(kKeySlots) void k_bucket_scan(unsigned *counts, unsigned *slots)
+{
+    __shared__ unsigned part[kKeySlots];
+    const int t = threadIdx.x;
+    unsigned *sl = slots + (size_t)blockIdx.x * kKeySlots;
+    const unsigned v = sl[t];
+    part[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kKeySlots; o <<= 1) {
+        const unsigned add = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    sl[t] = part[t] - v;
+    if (t == kKeySlots - 1) counts[blockIdx.x] = part[t];
+}
+
+__global__ void k_bucket_place(const OpDesc *__restrict__ ops, unsigned long long nops,
+                               const KeyDev *__restrict__ keys, int nkeys, unsigned long long in_words,
+                               unsigned long long out_words, unsigned *slots, unsigned *lists,
+                               unsigned long long cap)
+{
+    const unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nops) return;
+    const OpDesc op = ops[i];
+    const int b = op_bucket(op, keys, nkeys, in_words, out_words);
+    if (b < 0) return;
+    const unsigned at = atomicAdd(&slots[b * kKeySlots + (op.key_id % kKeySlots)], 1u);
+    lists[(unsigned long long)b * cap + at] = (unsigned)i;
 }
 
 // ---- the keyset ------------------------------------------------------------------
@@ -280,7 +322,8 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
     if (st != RSA_OK) return st;
     const size_t cap = (ws_bytes - kWsHeader) / ((size_t)kMaxBuckets * sizeof(unsigned));
     unsigned *hdr = static_cast<unsigned *>(workspace);
-    unsigned *counts = hdr, *counters = hdr + kMaxBuckets, *lists = hdr + 2 * kMaxBuckets;
+    unsigned *counts = hdr, *counters = hdr + kMaxBuckets, *slots = hdr + 2 * kMaxBuckets;
+    unsigned *lists = slots + (size_t)kMaxBuckets * kKeySlots;
     int nkeys;
     unsigned mask;
     {
@@ -288,11 +331,16 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         nkeys = ks->nkeys;
         mask = ks->class_mask;
     }
-    hipLaunchKernelGGL(k_bucket_clear, dim3(1), dim3(64), 0, stream, hdr);
-    hipLaunchKernelGGL(k_bucket_fill, dim3((unsigned)((nops + 255) / 256)), dim3(256), 0, stream,
-                       reinterpret_cast<const OpDesc *>(ops), (unsigned long long)nops, ks->keys, nkeys,
-                       (unsigned long long)in_words, (unsigned long long)out_words, counts, lists,
-                       (unsigned long long)cap, errs);
+    const unsigned op_blocks = (unsigned)((nops + 255) / 256);
+    const OpDesc *od = reinterpret_cast<const OpDesc *>(ops);
+    hipLaunchKernelGGL(k_bucket_clear, dim3((unsigned)((kWsHeader / sizeof(unsigned) + 255) / 256)), dim3(256), 0,
+                       stream, hdr);
+    hipLaunchKernelGGL(k_bucket_count, dim3(op_blocks), dim3(256), 0, stream, od, (unsigned long long)nops, ks->keys,
+                       nkeys, (unsigned long long)in_words, (unsigned long long)out_words, slots, errs);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(kMaxBuckets), dim3(kKeySlots), 0, stream, counts, slots);
+    hipLaunchKernelGGL(k_bucket_place, dim3(op_blocks), dim3(256), 0, stream, od, (unsigned long long)nops,
+                       ks->keys, nkeys, (unsigned long long)in_words, (unsigned long long)out_words, slots, lists,
+                       (unsigned long long)cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return status_of(e);
     int cus = 0;

@@ -10,8 +10,9 @@
 // added, so an operation starts directly with its exponentiation.
 //
 // Operations are grouped on the device into buckets of one (width class,
-// kind); each bucket is served by a persistent kernel whose waves claim
-// NG operations at a time from an atomic counter until the bucket is empty.
+// kind), each ordered by key; each bucket is served by a persistent kernel
+// whose workgroups claim a chunk of operations at a time from an atomic
+// counter until the bucket is empty.
 #pragma once
 
 #include "modexp_kernels.hpp"
@@ -146,25 +147,36 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
 }
 
 // Bucket of CRT decryptions for keys of one width class: H limbs of radix
-// 2^B hold p and q; two groups (p, q) per operation.
+// 2^B hold p and q.  A workgroup of two waves claims NG = 64 / G operations
+// at a time: wave 0 takes their halves modulo p, wave 1 those modulo q, one
+// operation per lane group, so a chunk of one key's operations (the bucket
+// lists are ordered by key) gives each wave a single exponent.  m_q reaches
+// wave 0 through wave 1's LDS region; wave 0 recombines and stores.
 template <int H, int G, int B>
-__global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
-                                                const unsigned *__restrict__ list, const unsigned *count_p,
-                                                unsigned *counter, const uint32_t *__restrict__ in_pool,
-                                                uint32_t *out_pool, int w)
+__global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
+                                                 const unsigned *__restrict__ list, const unsigned *count_p,
+                                                 unsigned *counter, const uint32_t *__restrict__ in_pool,
+                                                 uint32_t *out_pool, int w)
 {
     using Ar = Arith<H, G, B>;
     using Ly = Layout<H, G>;
-    constexpr int L = H / G, NG = 64 / G, NP = NG / 2;
-    static_assert(NG >= 2, "a wave holds at least one pair of groups");
-    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
+    constexpr int L = H / G, NG = 64 / G;
+    __shared__ unsigned chunk;
+    const int half = (int)(threadIdx.x >> 6);
+    const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
+    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + half * region;
+    uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + region;     // wave 1's region
     const int g = grp_index<G>(), r = grp_lane<G>();
-    const int half = g & 1;
     const unsigned count = *count_p;
     for (;;) {
-        const unsigned base = claim(counter, NP);
-        if (base >= count) break;
-        const unsigned idx = base + (g >> 1);
+        // Wave 0 reaches this barrier after Garner has read the previous
+        // chunk's m_q, and wave 1 reads `chunk` before the barrier below:
+        // neither the claim nor wave 1's next use of its region overtakes.
+        if (threadIdx.x == 0) chunk = atomicAdd(counter, (unsigned)NG);
+        __syncthreads();
+        const unsigned base = chunk;
+        if (base >= count) break;                     // the same for both waves
+        const unsigned idx = base + g;
         const bool live = idx < count;
         const OpDesc op = ops[live ? list[idx] : list[base]];
         const KeyDev &k = keys[op.key_id];
@@ -190,12 +202,17 @@ __global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys,
         group_modexp<H, G, B>(A, xt, half ? k.dq : k.dp, hl, live, n, n0inv, one, lds, w);
         from_mont<H, G, B>(A, lds, n, n0inv);
 
+        if (half) {
+            lds_sync();
+            lds_put<H, G>(qlds, A);
+        }
+        __syncthreads();
+        if (half) continue;
+
+        // Garner: h = qinv * (m_p - m_q) mod p, m = m_q + h * q
         uint32_t mq[L], qv[L], hh[L];
-        lds_sync();
-        lds_put<H, G>(lds, A);
-        lds_sync();
-        lds_get<H, G>(mq, lds, g ^ 1);
-        {
+        lds_get<H, G>(mq, qlds, g);
+        {   // delta = m_p - m_q mod p  (m_q < q < p)
             uint32_t d[L], e[L];
             const uint32_t neg = Ar::sub(d, A, mq);
 #pragma unroll
@@ -204,7 +221,7 @@ __global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys,
 #pragma unroll
             for (int j = 0; j < L; ++j) A[j] = neg ? e[j] : d[j];
         }
-        load_raw<H, G>(qv, k.cp[radix_slot<B>()].xr, live && !half);     // qinv * R mod p
+        load_raw<H, G>(qv, k.cp[radix_slot<B>()].xr, live);     // qinv * R mod p
         mont_mul_reg<H, G, B>(hh, A, qv, lds, n, n0inv);
         lds_sync();
         lds_put<H, G>(lds, hh);
@@ -213,13 +230,13 @@ __global__ __launch_bounds__(64) void k_ops_crt(const KeyDev *__restrict__ keys,
         auto sink = [&](int i, uint32_t v) {
             if (r == 0) stage[i] = v;
         };
-        uint32_t high[L], other[L];
-        Ar::load(other, k.q, hl, 0, live);
-        Ar::mul_wide(high, mq, other, lds, sink);
+        uint32_t high[L], qn[L];
+        Ar::load(qn, k.q, hl, 0, live);
+        Ar::mul_wide(high, mq, qn, lds, sink);
 #pragma unroll
         for (int j = 0; j < L; ++j) stage[H + r * L + j] = high[j];
         lds_sync();
-        if (live && !half) {
+        if (live) {
             uint32_t *o = out_pool + op.out_off;
             if constexpr (B == 32) {
                 for (int wd = r; wd < full; wd += G) o[wd] = stage[wd];

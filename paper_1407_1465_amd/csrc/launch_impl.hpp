@@ -55,8 +55,8 @@ hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned 
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                           hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, B, w), stream, keys, ops,
-                       list, count, counter, in_pool, out_pool, w);
+    hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(128), 2 * lds_bytes_for(S, G, B, w), stream, keys,
+                       ops, list, count, counter, in_pool, out_pool, w);
     return hipGetLastError();
 }
 
@@ -67,7 +67,8 @@ int ops_blocks_per_cu(int kind, int w)
     const size_t lds = lds_bytes_for(S, G, B, w);
     hipError_t e = kind == 0
         ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_enc<S, G, B>), 64, lds)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B>), 64, lds);
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B>), 128,
+                                                       2 * lds);
     return e == hipSuccess ? nb : 0;
 }
 
