@@ -213,6 +213,16 @@ __device__ __forceinline__ uint32_t grp_max(uint32_t v)
     return v;
 }
 
+// c held in a VGPR rather than as an instruction literal, so that a DPP lane
+// move feeding an operation with c can fold into one DPP-modified VOP2
+// instruction (their second operand must be a VGPR).
+__device__ __forceinline__ uint32_t vgpr_const(uint32_t c)
+{
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "i"(c));
+    return v;
+}
+
 // The first active lane's value of a pointer (wave-uniform from here on).
 __device__ __forceinline__ const uint32_t *first_lane_ptr(const uint32_t *p)
 {
