@@ -84,12 +84,11 @@ def sqr_products(s: int) -> int:
 
 def symmetric_squarings(plan) -> bool:
     """Whether the plan's kernel squares with one product per limb pair:
-    radix 2^29 with the multiplier in registers (2 or 4 lanes per
-    exponentiation) and at most 20 limbs per lane.  Its waves do so when
-    all their exponents are equal (one key, or a public exponent); the
-    count below credits every squaring at the symmetric cost, so a wave
-    that mixes exponents is charged less than it computes."""
-    return plan.radix_bits == 29 and plan.lanes_per_op in (2, 4) and 3 * plan.limbs_per_lane <= 62
+    radix 2^29 with at most 20 limbs per lane.  Its waves do so when all
+    their exponents are equal (one key, or a public exponent); the count
+    below credits every squaring at the symmetric cost, so a wave that
+    mixes exponents is charged less than it computes."""
+    return plan.radix_bits == 29 and 3 * plan.limbs_per_lane <= 62
 
 
 def exp_products(e: int, plan, s: int) -> int:

@@ -85,6 +85,12 @@ int rsa_modexp_batch(const uint32_t *base, const uint32_t *exp, const uint32_t *
  * must be even, 2 <= limbs <= RSA_MAX_LIMBS.  Convention p > q and
  * qinv = q^-1 mod p; p, q odd and > 1.  Violations are data errors.
  * c must be < p*q (it is the caller's ciphertext).
+ * Messages under the same key are processed together (one exponent per
+ * wave): for more than one workgroup's worth of messages the call orders
+ * them by a hash of their key words in scratch taken from the device's
+ * default memory pool with stream-ordered allocation on `stream` (4 bytes
+ * per message + 256 KiB, released on the same stream); if that allocation
+ * fails it runs in the given order.  The order never changes a result.
  */
 int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *q,
                           const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,

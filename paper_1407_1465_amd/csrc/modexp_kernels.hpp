@@ -58,13 +58,21 @@ struct Arith {
     {
         rmont_mul_regs<S, G, B, true>(r, a, b, n, n0inv);
     }
-    // Lazy square with a in registers; symmetric (rmont_sqr_regs) where kSqr.
-    static constexpr bool kSqr = (G == 2 || G == 4) && rsqr_fits<B, L>();
+    // Lazy squares, symmetric (one product per limb pair) where kSqr: with a
+    // in registers (G = 2 or 4) or also staged in the group's slot of abuf.
+    static constexpr bool kSqr = rsqr_fits<B, L>();
     static __device__ __forceinline__ void sqr_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
                                                          const uint32_t (&n)[L], uint32_t n0inv)
     {
-        if constexpr (kSqr) rmont_sqr_regs<S, G, B, true>(r, a, n, n0inv);
+        if constexpr (kSqr && (G == 2 || G == 4)) rmont_sqr_regs<S, G, B, true>(r, a, n, n0inv);
         else rmont_mul_regs<S, G, B, true>(r, a, a, n, n0inv);
+    }
+    static __device__ __forceinline__ void sqr_lds_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                        const uint32_t *abuf, const uint32_t (&n)[L],
+                                                        uint32_t n0inv)
+    {
+        if constexpr (kSqr) rmont_sqr<S, G, B, true>(r, a, abuf, n, n0inv);
+        else rmont_mul<S, G, B, true>(r, a, abuf, n, n0inv);
     }
     template <typename Sink>
     static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
@@ -127,6 +135,12 @@ struct Arith<S, G, 32> {
                                                          const uint32_t (&n)[L], uint32_t n0inv)
     {
         rsagpu::mont_mul_regs<S, G>(r, a, a, n, n0inv);
+    }
+    static __device__ __forceinline__ void sqr_lds_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                        const uint32_t *abuf, const uint32_t (&n)[L],
+                                                        uint32_t n0inv)
+    {
+        rsagpu::mont_mul<S, G>(r, a, abuf, n, n0inv);
     }
     template <typename Sink>
     static __device__ __forceinline__ void mul_wide(uint32_t (&hi)[L], const uint32_t (&init)[L],
@@ -302,8 +316,9 @@ struct ExpBits {
 // table entry.  Where squarings can be symmetric (Arith::kSqr) and every
 // live group of the wave has the same exponent words (one key's exponent,
 // or a public exponent), the wave instead follows one schedule: its
-// squarings multiply each pair of limbs once (rmont_sqr_regs) and its table
-// products read one entry for all groups.  Every product is lazy (A and the
+// squarings multiply each pair of limbs once (rmont_sqr_regs, or rmont_sqr
+// with A staged in the operand buffer) and its table products read one entry
+// for all groups.  Every product is lazy (A and the
 // table stay below 2n in redundant limbs); the caller's from_mont makes the
 // result canonical.
 template <int S, int G, int B>
@@ -330,7 +345,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     // this group's exponent length (its lanes scan slices of the words) and,
     // where squarings can be symmetric, whether every live group of the wave
     // has group 0's exponent: then the whole wave follows one schedule
-    constexpr bool UNI = REG && Ar::kSqr;
+    constexpr bool UNI = Ar::kSqr;
     const int el = use_exp ? elimbs : 0;
     uint32_t ebits = 0;
     bool same = true;
@@ -432,11 +447,24 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
             while (__builtin_amdgcn_readfirstlane(pos) >= 0) {
                 next_window();
                 const int nsq = __builtin_amdgcn_readfirstlane(sq), ui = __builtin_amdgcn_readfirstlane(mi);
-                for (int q = 0; q < nsq; ++q) Ar::sqr_regs_lazy(A, A, n, n0inv);
+                for (int q = 0; q < nsq; ++q) {
+                    if constexpr (REG) {
+                        Ar::sqr_regs_lazy(A, A, n, n0inv);
+                    } else {
+                        lds_sync();
+                        lds_put<S, G>(abuf, A);
+                        lds_sync();
+                        Ar::sqr_lds_lazy(A, A, abuf, n, n0inv);
+                    }
+                }
                 if (ui >= 0) {
-                    uint32_t tb[L];
-                    lds_get<S, G>(tb, tbl + ui * Ly::WORDS, g);
-                    mul_regs(A, A, tb);
+                    if constexpr (REG) {
+                        uint32_t tb[L];
+                        lds_get<S, G>(tb, tbl + ui * Ly::WORDS, g);
+                        mul_regs(A, A, tb);
+                    } else {
+                        mul_lds(A, A, tbl + ui * Ly::WORDS);
+                    }
                 }
             }
             return;

@@ -44,8 +44,10 @@ __global__ void k_order_count(const uint32_t *p, const uint32_t *dp, const uint3
     atomicAdd(&cnt[key_bucket(p, dp, dq, i, hl)], 1u);
 }
 
-// Exclusive prefix sum of the bucket counts, in place (one workgroup of
-// 1024 threads, kBuckets / 1024 buckets per thread).
+// Exclusive prefix sum of the bucket counts, in place, in an order of the
+// buckets that keeps the loads coalesced: thread t owns buckets t, t + 1024,
+// t + 2048, ... and the threads' runs follow each other (any order of the
+// buckets groups the messages the same way).  One workgroup of 1024 threads.
 __global__ __launch_bounds__(1024) void k_order_scan(unsigned *cnt)
 {
     constexpr int PER = kBuckets / 1024;
@@ -54,7 +56,7 @@ __global__ __launch_bounds__(1024) void k_order_scan(unsigned *cnt)
     unsigned v[PER], s = 0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        v[k] = cnt[t * PER + k];
+        v[k] = cnt[k * 1024 + t];
         s += v[k];
     }
     part[t] = s;
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(1024) void k_order_scan(unsigned *cnt)
     unsigned run = part[t] - s;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        cnt[t * PER + k] = run;
+        cnt[k * 1024 + t] = run;
         run += v[k];
     }
 }

@@ -416,6 +416,43 @@ __device__ __forceinline__ void rmont_sqr_regs(uint32_t (&r)[S / G], const uint3
     rmont_finish<S, G, B, LAZY>(r, acc, n);
 }
 
+// The same squaring with the group's limbs of a also staged in its slot of
+// LDS buffer abuf (any G): block q reads lane q's limbs there instead of
+// broadcasting them by DPP.
+template <int S, int G, int B, bool LAZY>
+__device__ __forceinline__ void rmont_sqr(uint32_t (&r)[S / G], const uint32_t (&a)[S / G], const uint32_t *abuf,
+                                          const uint32_t (&n)[S / G], uint32_t n0inv)
+{
+    using Ly = Layout<S, G>;
+    constexpr int L = Ly::L, V = Ly::V;
+    static_assert(rsqr_fits<B, L>(), "limbs per lane too large for a squaring in this radix");
+    const int g = grp_index<G>(), lane = grp_lane<G>();
+    uint64_t acc[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[j] = 0;
+    for (int q = 0; q < G; ++q) {
+        uint32_t bv[L];
+#pragma unroll
+        for (int k = 0; k < L; k += V) {
+            typename VecT<V>::T v = *reinterpret_cast<const typename VecT<V>::T *>(abuf + Ly::at(q * L + k, g));
+            const uint32_t *pv = reinterpret_cast<const uint32_t *>(&v);
+#pragma unroll
+            for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
+        }
+        const bool above = lane > q, own = lane == q;
+#pragma unroll
+        for (int k = 0; k < L; ++k) {
+            const uint32_t b2 = bv[k] << 1;
+            const uint32_t bd = above ? b2 : (own ? a[k] : 0u);
+            acc[(2 * k) % L] += (uint64_t)a[k] * bd;
+#pragma unroll
+            for (int j = k + 1; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * b2;
+            rcios_reduce<S, G, B>(acc, k, n, n0inv);
+        }
+    }
+    rmont_finish<S, G, B, LAZY>(r, acc, n);
+}
+
 // (low, high) = init + a * b (no reduction), b in LDS; lane 0 of the group
 // passes low limb i to sink(i, limb); high gets the upper S limbs.
 template <int S, int G, int B, typename Sink>

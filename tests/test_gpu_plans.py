@@ -72,7 +72,7 @@ def test_instance_modexp(B, S, G, plan_guard):
     assert rsagpu.device_errors() == 0
 
 
-@pytest.mark.parametrize("B,S,G", [i for i in INSTANCES if i[2] <= 4])
+@pytest.mark.parametrize("B,S,G", INSTANCES)
 def test_instance_modexp_shared_exponent(B, S, G, plan_guard):
     """Waves whose groups all carry the same exponent words (one key's
     exponent, a public exponent) run one schedule for the whole wave with
@@ -113,8 +113,8 @@ def test_instance_crt(B, S, G, plan_guard):
     keys = W.make_keys(bits, 4242 + bits, 2)
     L = keys[0].limbs
     h = L // 2
-    pairs = 32 // G
-    count = pairs + 3 if bits >= 2048 else 2 * pairs + 3
+    ng = 64 // G                          # messages per workgroup
+    count = 2 * ng + 3                    # key-ordered: at least one workgroup of one key
     rng = random.Random(S * G + B)
     key_of = np.arange(count) % 2
     cs = [rng.randrange(keys[k].n) for k in key_of]
