@@ -21,7 +21,10 @@ line carries
 Other workloads (--workload): rsa64, rsa1024 (full-d decryption, no CRT),
 enc2048 (e = 65537 encryption of the default batch), mixed (32768 operations
 over 1024..4096-bit keys in one rsa_ops_batch call), serve (Poisson requests
-through the continuous-batching server: p50/p99 latency and throughput).
+through the continuous-batching server: p50/p99 latency and throughput),
+paper (the paper's own Section 10 experiment: one-word keys n = 131*137 and
+1009*509, e = 131, messages 0..800 at every data size of Tables 1 and 2,
+beside the times the tables print, whose unit the paper leaves unclear).
 """
 import argparse
 import json
@@ -190,7 +193,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="crt2048",
-                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve"])
+                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve", "paper"])
     ap.add_argument("--count", type=int, default=0, help="messages (0: the workload's size)")
     ap.add_argument("--cpu-sample", type=int, default=1536,
                     help="messages the CPU oracle processes for the baseline (0: skip)")
@@ -343,6 +346,37 @@ def main():
         line["roofline"] = roofline(products, ms, "k_ops_* (all buckets)")
         value = nops / (ms / 1e3)
         ks.close()
+
+    elif args.workload == "paper":
+        # The paper's own experiment (Section 10, Tables 1 and 2): one-word
+        # moduli, e = 131, messages 0..800, at every data size the tables
+        # list; encryption and decryption (round trip checked) per size.
+        rows = []
+        for t, key in sorted(W.PAPER_TABLE_KEYS.items()):
+            for i, N in enumerate(W.PAPER_TABLE_SIZES):
+                msgs = W.paper_table_messages(N)
+                m = dev(msgs)
+                e = dev(np.full((N, 1), key.e, dtype=np.uint32))
+                d = dev(np.full((N, 1), key.d, dtype=np.uint32))
+                n = dev(np.full((N, 1), key.n, dtype=np.uint32))
+                c = torch.empty_like(m)
+                back = torch.empty_like(m)
+                ms_enc, _ = timed(lambda: rsagpu.modexp(m, e, n, out=c), args.steps, args.warmup, torch)
+                ms_dec, _ = timed(lambda: rsagpu.modexp(c, d, n, out=back), args.steps, args.warmup, torch)
+                if not torch.equal(back, m):
+                    raise SystemExit("paper-table round trip failed (table %d, %d messages)" % (t, N))
+                rows.append({"table": t, "n": key.n, "e": key.e, "d": key.d, "messages": N,
+                             "encrypt_ms": ms_enc, "decrypt_ms": ms_dec,
+                             "paper_gpu_time_as_printed": W.PAPER_TABLE_GPU_TIME[t][i]})
+        last = rows[-1]
+        ms, wall = last["encrypt_ms"], sum(r["encrypt_ms"] + r["decrypt_ms"] for r in rows) * args.steps / 1e3
+        plan = rsagpu.get_plan(1, 0)
+        line.update(metric="paper Section 10 workload: one-word RSA encryptions/s (n = 1009*509, e = 131, "
+                           "32768 messages 0..800) on 1 GPU", unit="encryptions/s",
+                    config={"workload": "paper-tables-1-2", "radix_bits": plan.radix_bits,
+                            "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
+        line["rows"] = rows
+        value = last["messages"] / (ms / 1e3)
 
     else:   # serve
         from paper_1407_1465_amd.serve import GpuExecutor, Server, poisson_requests

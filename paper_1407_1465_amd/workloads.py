@@ -430,3 +430,47 @@ def workload_c4(total: int = 32768, keys_per_size: int = 16) -> MixedWorkload:
     (e = 65537), half CRT decryptions, 16 keys per size."""
     return mixed_workload("rsa-mixed-1k-4k", [1024, 2048, 3072, 4096], [4, 8, 2, 1], total,
                           keys_per_size, SEED_BASE + 4)
+
+
+# ---------------------------------------------------------------------------
+# the paper's own experiment (Section 10): one-word moduli, 8-bit exponents
+# ---------------------------------------------------------------------------
+
+@dataclass
+class PaperTableKey:
+    """A key of the paper's experiments: n printed in Tables 1 and 2, e an
+    8-bit exponent.  Table 1 uses n = 131 * 137 with e = 131 (the example key
+    of Section 2); its printed private exponent 137 does not invert e modulo
+    phi(n) = 17680, so d here is the inverse, 14171.  Table 2's caption
+    prints 1005 * 509 while its text prints 1009 * 509 (1005 is not prime):
+    n = 513581; the paper gives no exponent for it, so it takes the same
+    8-bit e = 131, which is coprime to phi(n) = 512064."""
+    table: int
+    p: int
+    q: int
+    e: int
+
+    @property
+    def n(self) -> int:
+        return self.p * self.q
+
+    @property
+    def d(self) -> int:
+        return pow(self.e, -1, (self.p - 1) * (self.q - 1))
+
+
+PAPER_TABLE_KEYS = {1: PaperTableKey(1, 137, 131, 131), 2: PaperTableKey(2, 1009, 509, 131)}
+# Data sizes of Tables 1 and 2 (the last two printed as 16392 and 32784,
+# read as 16384 and 32768: blocks x threads per block).
+PAPER_TABLE_SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384, 32768)
+# Times the tables print (units as printed, likely not seconds), by data size.
+PAPER_TABLE_GPU_TIME = {
+    1: (7.56, 7.25, 6.86, 5.38, 5.68, 6.27, 7.21, 9.25),
+    2: (6.08, 6.52, 6.69, 5.53, 6.58, 6.66, 7.81, 8.76),
+}
+
+
+def paper_table_messages(count: int, seed: int = SEED_BASE + 6) -> np.ndarray:
+    """``count`` messages uniform in 0..800 (the paper's test messages cover
+    the ASCII table), one 32-bit limb each: (count, 1) uint32."""
+    return uniform_below(801, count, seed, 1)

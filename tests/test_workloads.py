@@ -79,3 +79,22 @@ def test_workload_shapes_small():
     assert w3.key_of.tolist() == [i % 4 for i in range(40)]
     for i, m in enumerate(W.limbs_to_ints(w3.ctxt)):
         assert m < w3.keys[i % 4].n
+
+
+def test_paper_table_keys():
+    """The keys of the paper's Section 10 experiment: Table 1's n = 131 * 137
+    with the Section 2 example exponent 131 (whose printed partner 137 is not
+    its inverse: 131 * 137 mod phi(n) = 267), Table 2's n = 1009 * 509 (the
+    caption's 1005 is composite); d inverts e modulo phi(n) and messages
+    stay in 0..800."""
+    k1, k2 = W.PAPER_TABLE_KEYS[1], W.PAPER_TABLE_KEYS[2]
+    assert (k1.n, k2.n) == (17947, 513581)
+    assert (131 * 137) % ((k1.p - 1) * (k1.q - 1)) == 267
+    assert k1.d == 14171
+    for k in (k1, k2):
+        assert (k.e * k.d) % ((k.p - 1) * (k.q - 1)) == 1
+        assert all(pow(pow(m, k.e, k.n), k.d, k.n) == m for m in range(801))
+    m = W.paper_table_messages(32768)
+    assert m.shape == (32768, 1) and int(m.min()) == 0 and int(m.max()) == 800
+    assert np.array_equal(m, W.paper_table_messages(32768))
+    assert len(W.PAPER_TABLE_SIZES) == len(W.PAPER_TABLE_GPU_TIME[1]) == len(W.PAPER_TABLE_GPU_TIME[2])
