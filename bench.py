@@ -24,7 +24,8 @@ over 1024..4096-bit keys in one rsa_ops_batch call), serve (Poisson requests
 through the continuous-batching server: p50/p99 latency and throughput),
 paper (the paper's own Section 10 experiment: one-word keys n = 131*137 and
 1009*509, e = 131, messages 0..800 at every data size of Tables 1 and 2,
-beside the times the tables print, whose unit the paper leaves unclear).
+beside the times the tables print, whose unit the paper leaves unclear),
+keygen (4096-bit key generation with the Miller-Rabin rounds on the GPU).
 """
 import argparse
 import json
@@ -193,7 +194,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="crt2048",
-                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve", "paper"])
+                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve", "paper", "keygen"])
     ap.add_argument("--count", type=int, default=0, help="messages (0: the workload's size)")
     ap.add_argument("--cpu-sample", type=int, default=1536,
                     help="messages the CPU oracle processes for the baseline (0: skip)")
@@ -377,6 +378,29 @@ def main():
                             "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
         line["rows"] = rows
         value = last["messages"] / (ms / 1e3)
+
+    elif args.workload == "keygen":
+        # Section 3.1 key generation with the Miller-Rabin rounds batched on
+        # the GPU: 16 seeded 4096-bit keys, equal to the CPU generator's.
+        from paper_1407_1465_amd import keygen
+        nk, bits, seed = 16, 4096, W.SEED_BASE + 7
+        keygen.make_keys_gpu(1024, seed, 2)                # warm-up (library load, kernels)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        keys = keygen.make_keys_gpu(bits, seed, nk)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        t2 = time.perf_counter()
+        cpu_key = W.make_key(bits, W.derive_seed(seed, bits, 0))
+        cpu_s = time.perf_counter() - t2
+        if keys[0] != cpu_key:
+            raise SystemExit("GPU key generation differs from the CPU generator")
+        ms = wall * 1e3
+        line.update(metric="4096-bit RSA key generation (Miller-Rabin on the GPU) keys/s on 1 GPU",
+                    unit="keys/s", config={"workload": "keygen-4096", "keys": nk, "modulus_bits": bits})
+        line["cpu_keygen_one_thread"] = {"value": 1.0 / cpu_s, "unit": "keys/s",
+                                         "sample": "key 0 of the same seeds, Python pow"}
+        value = nk / wall
 
     else:   # serve
         from paper_1407_1465_amd.serve import GpuExecutor, Server, poisson_requests

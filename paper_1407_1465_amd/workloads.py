@@ -474,3 +474,18 @@ def paper_table_messages(count: int, seed: int = SEED_BASE + 6) -> np.ndarray:
     """``count`` messages uniform in 0..800 (the paper's test messages cover
     the ASCII table), one 32-bit limb each: (count, 1) uint32."""
     return uniform_below(801, count, seed, 1)
+
+
+def text_to_packets(text: str) -> List[int]:
+    """Section 2's encoding of a text: letters a..z as 00..25 (other
+    characters dropped), two letters per packet as a four-digit decimal
+    number (a trailing single letter pads with 'x' = 23)."""
+    codes = [ord(ch) - 97 for ch in text.lower() if "a" <= ch <= "z"]
+    if len(codes) % 2:
+        codes.append(23)
+    return [codes[i] * 100 + codes[i + 1] for i in range(0, len(codes), 2)]
+
+
+def packets_to_text(packets: Sequence[int]) -> str:
+    """Inverse of text_to_packets (letters only)."""
+    return "".join(chr(97 + p // 100) + chr(97 + p % 100) for p in packets)

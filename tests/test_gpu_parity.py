@@ -228,6 +228,22 @@ def test_paper_table_keys_round_trip(table):
     assert rsagpu.device_errors() == 0
 
 
+def test_section2_text_example_end_to_end():
+    """Section 2's example flow on the GPU: "parallel encryption" as
+    two-letter packets, encrypted with (e, n) = (131, 17947), decrypted with
+    d = 14171 (the inverse of 131 mod phi(n); the printed 137 is not), back
+    to the text."""
+    key = W.PAPER_TABLE_KEYS[1]
+    packets = W.text_to_packets("parallel encryption")
+    N = len(packets)
+    m = np.array(packets, dtype=np.uint32).reshape(N, 1)
+    col = lambda v: np.full((N, 1), v, dtype=np.uint32)
+    c = host(rsagpu.modexp(dev(m), dev(col(key.e)), dev(col(key.n))))
+    assert [int(v) for v in c[:, 0]] == [pow(p, key.e, key.n) for p in packets]
+    back = host(rsagpu.modexp(dev(c), dev(col(key.d)), dev(col(key.n))))
+    assert W.packets_to_text([int(v) for v in back[:, 0]]) == "parallelencryption"
+
+
 def test_workload_rsa2048_crt_sampled_and_roundtrip():
     """64 keys of 2048 bits, 16384 messages round-robin: CRT decryption of the
     whole batch sampled against the oracle, plus the encrypt/decrypt round trip."""

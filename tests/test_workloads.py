@@ -98,3 +98,18 @@ def test_paper_table_keys():
     assert m.shape == (32768, 1) and int(m.min()) == 0 and int(m.max()) == 800
     assert np.array_equal(m, W.paper_table_messages(32768))
     assert len(W.PAPER_TABLE_SIZES) == len(W.PAPER_TABLE_GPU_TIME[1]) == len(W.PAPER_TABLE_GPU_TIME[2])
+
+
+def test_text_packets_match_section2_golden():
+    """The packet codec against the packets printed for the Section 2
+    example (tests/golden/packets_sec2.txt)."""
+    import os
+    golden = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "packets_sec2.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.rstrip("\n").split(" ", 1)
+                golden[k] = v
+    packets = [int(p) for p in golden["packets"].split()]
+    assert W.text_to_packets(golden["text"]) == packets
+    assert W.packets_to_text(packets) == golden["text"].replace(" ", "")
