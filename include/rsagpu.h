@@ -103,7 +103,8 @@ int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *
  * radix (padded_limbs), lanes per exponentiation (G), limbs per lane
  * (padded_limbs / G), window width in exponent bits (a sliding window over
  * the 2^(window_bits-1) odd powers, paper Section 3.6.5) and the LDS bytes
- * per 64-lane workgroup.
+ * per wave (the CRT kernels run workgroups of two waves, one per half, and
+ * take twice that per workgroup).
  * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
  * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
  * operations inside rsa_ops_batch (separate plans: its buckets are smaller
