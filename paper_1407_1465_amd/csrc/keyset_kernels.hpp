@@ -122,6 +122,7 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
 {
     using Ar = Arith<S, G, B>;
     constexpr int L = S / G, NG = 64 / G;
+    constexpr bool OWN = B != 32 && !standard_s29(S);     // constants not in the keyset's limb count
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
     const int g = grp_index<G>();
     const unsigned count = *count_p;
@@ -136,9 +137,13 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
         uint32_t n[L], x[L], one[L], r2[L], xt[L], A[L];
         Ar::load(n, k.n, k.words, 0, live);
         Ar::load(x, in_pool + op.in_off, k.words, 0, live);
-        load_raw<S, G>(one, mc.one, live);
-        load_raw<S, G>(r2, mc.r2, live);
         const uint32_t n0inv = Ar::n0inv(grp_bcast0<G>(n[0]) | 1u);
+        if constexpr (OWN) {
+            mont_setup<S, G, B>(one, r2, n, n0inv, live, lds, lds + Layout<S, G>::WORDS);
+        } else {
+            load_raw<S, G>(one, mc.one, live);
+            load_raw<S, G>(r2, mc.r2, live);
+        }
         mont_mul_reg<S, G, B>(xt, x, r2, lds, n, n0inv);
         group_modexp<S, G, B>(A, xt, k.e, k.words, live, n, n0inv, one, lds, w);
         from_mont<S, G, B>(A, lds, n, n0inv);
@@ -161,6 +166,7 @@ __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys
     using Ar = Arith<H, G, B>;
     using Ly = Layout<H, G>;
     constexpr int L = H / G, NG = 64 / G;
+    constexpr bool OWN = B != 32 && !standard_s29(H);     // constants not in the keyset's limb count
     __shared__ unsigned chunk;
     const int half = (int)(threadIdx.x >> 6);
     const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
@@ -188,17 +194,24 @@ __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys
         Ar::load(chi, in_pool + op.in_off, full, B * H, live);
         const uint32_t n0inv = Ar::n0inv(grp_bcast0<G>(n[0]) | 1u);
         // xt = c * R mod m = c_lo * R^2 * R^-1 + c_hi * R^3 * R^-1  (c = c_lo + c_hi * R)
-        uint32_t xt[L], t2[L];
-        load_raw<H, G>(rk, mc.r2, live);
-        mont_mul_reg<H, G, B>(xt, clo, rk, lds, n, n0inv);
-        load_raw<H, G>(rk, mc.r3, live);
-        mont_mul_reg<H, G, B>(t2, chi, rk, lds, n, n0inv);
+        uint32_t xt[L], t2[L], r2[L];
+        if constexpr (OWN) {
+            mont_setup<H, G, B>(one, r2, n, n0inv, live, lds, lds + Ly::WORDS);
+            mont_mul_reg<H, G, B>(xt, clo, r2, lds, n, n0inv);
+            mont_mul_reg<H, G, B>(rk, r2, r2, lds, n, n0inv);        // R^3 mod m
+            mont_mul_reg<H, G, B>(t2, chi, rk, lds, n, n0inv);
+        } else {
+            load_raw<H, G>(rk, mc.r2, live);
+            mont_mul_reg<H, G, B>(xt, clo, rk, lds, n, n0inv);
+            load_raw<H, G>(rk, mc.r3, live);
+            mont_mul_reg<H, G, B>(t2, chi, rk, lds, n, n0inv);
+            load_raw<H, G>(one, mc.one, live);
+        }
         {
             const uint32_t ovf = Ar::add(xt, t2);
             Ar::cond_sub(xt, ovf, n);
         }
         uint32_t A[L];
-        load_raw<H, G>(one, mc.one, live);
         group_modexp<H, G, B>(A, xt, half ? k.dq : k.dp, hl, live, n, n0inv, one, lds, w);
         from_mont<H, G, B>(A, lds, n, n0inv);
 
@@ -221,7 +234,12 @@ __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys
 #pragma unroll
             for (int j = 0; j < L; ++j) A[j] = neg ? e[j] : d[j];
         }
-        load_raw<H, G>(qv, k.cp[radix_slot<B>()].xr, live);     // qinv * R mod p
+        if constexpr (OWN) {
+            Ar::load(qv, k.qinv, hl, 0, live);
+            mont_mul_reg<H, G, B>(qv, qv, r2, lds, n, n0inv);     // qinv * R mod p
+        } else {
+            load_raw<H, G>(qv, k.cp[radix_slot<B>()].xr, live);  // qinv * R mod p
+        }
         mont_mul_reg<H, G, B>(hh, A, qv, lds, n, n0inv);
         lds_sync();
         lds_put<H, G>(lds, hh);

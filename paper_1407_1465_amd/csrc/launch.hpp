@@ -31,6 +31,16 @@ typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const 
 // Workgroups of an ops kernel resident per CU at window w (occupancy query).
 typedef int (*ops_occupancy)(int kind, int w);
 
+// Radix-2^29 limb counts of the width classes (29 * S >= 32 * width + 10, so
+// R > 2^10 n): the limb count a keyset's Montgomery constants are stored
+// with.  An instance with another S (the class's count rounded up to a
+// multiple of its lanes per group, for 16 lanes) computes its constants
+// itself.
+__host__ __device__ constexpr bool standard_s29(int S)
+{
+    return S == 18 || S == 28 || S == 36 || S == 56 || S == 72 || S == 112 || S == 144;
+}
+
 // Instances whose Montgomery products inside the exponentiation take the
 // multiplier from registers (1, 2 or 4 lanes per group: at most one DPP quad
 // permute per step); the others read it from LDS.

@@ -25,6 +25,9 @@ static const Instance kInstances[] = {
 static const int kClasses[] = {2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128};
 static const int kS29[] = {0, 0, 0, 0, 18, 28, 36, 56, 72, 112, 144};
 static const int kNumClasses = sizeof(kClasses) / sizeof(kClasses[0]);
+static_assert(standard_s29(18) && standard_s29(28) && standard_s29(36) && standard_s29(56) && standard_s29(72) &&
+                  standard_s29(112) && standard_s29(144),
+              "kS29 and standard_s29 list the same limb counts");
 
 // Default plan per class: limb radix 2^B, lanes per exponentiation G (limbs
 // per lane L = S / G) and window bits w, measured on large batches.  From
@@ -48,7 +51,10 @@ struct Plan {
 // Kinds 2 and 3 are the same operations inside rsa_ops_batch, whose buckets
 // are usually far smaller than a plain batch and run side by side: there a
 // narrower group (more waves per operation) and a smaller LDS footprint (room
-// for the other buckets' waves) pay off.
+// for the other buckets' waves) pay off.  For 4096-bit CRT halves, 16
+// lanes (S = 80) shorten one operation, which a bulk mixed batch waits for
+// at its end (11% less time), but cost 64% more instructions per operation,
+// which a loaded server pays in latency (p50 +18%); the default keeps 8.
 static const int kKinds = 4;
 static const Plan kDefault[kKinds][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
@@ -89,9 +95,12 @@ int class_index(int limbs)
 const Instance *find_instance(int i, int B, int G)
 {
     const int S = B == 32 ? kClasses[i] : (B == 29 ? kS29[i] : 0);
-    if (S == 0) return nullptr;
+    if (S == 0 || G <= 0) return nullptr;
+    // radix 2^29 with more lanes than the class's S divides into: the
+    // instance with S rounded up to a multiple of G, where one is compiled
+    const int Sw = (B == 29 && S % G) ? (S + G - 1) / G * G : S;
     for (const Instance &in : kInstances)
-        if (in.B == B && in.S == S && in.G == G) return &in;
+        if (in.B == B && in.S == Sw && in.G == G) return &in;
     return nullptr;
 }
 

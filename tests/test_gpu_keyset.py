@@ -86,6 +86,33 @@ def test_keyset_mixed_vs_oracle():
     ks.close()
 
 
+def test_keyset_sixteen_lane_plans_vs_oracle():
+    """Ops-batch plans on the 16-lane instances whose limb count is not the
+    keyset's (S = 80 for 2048-bit operands, 64 for 1536-bit): the kernels
+    compute their Montgomery constants themselves; 4096- and 3072-bit CRT
+    halves and 2048-bit encryptions against the oracle."""
+    touched = [(64, 3), (48, 3), (64, 2)]
+    try:
+        rsagpu.set_plan(64, 3, 29, 16, 4)
+        rsagpu.set_plan(48, 3, 29, 16, 4)
+        rsagpu.set_plan(64, 2, 29, 16, 3)
+        assert rsagpu.get_plan(64, 3).padded_limbs == 80
+        assert rsagpu.get_plan(48, 3).padded_limbs == 64
+        keys, kinds, kids, offs, pool, words = small_mix(5, sizes=(2048, 3072, 4096), per_size=2, count=40)
+        ks = make_keyset(keys)
+        out = run_ops(ks, kinds, kids, offs, pool, words)
+        want = oracle_ops(keys, kinds, kids, offs, pool)
+        for i in range(len(kinds)):
+            L = keys[kids[i]].limbs
+            assert np.array_equal(out[offs[i]:offs[i] + L], want[i]), "op %d (kind %d, %d bits)" % (
+                i, kinds[i], 32 * L)
+        assert rsagpu.device_errors() == 0
+        ks.close()
+    finally:
+        for limbs, kind in touched:
+            rsagpu.set_plan(limbs, kind, 0, 0, 0)
+
+
 def test_alone_equals_mixed():
     """Each request's result is the same alone and inside a busy mix."""
     keys, kinds, kids, offs, pool, words = small_mix(2, count=120)

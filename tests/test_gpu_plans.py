@@ -23,7 +23,7 @@ from paper_1407_1465_amd import rsagpu  # noqa: E402
 DEF = os.path.join(ROOT, "paper_1407_1465_amd", "csrc", "instances.def")
 INSTANCES = [tuple(map(int, m)) for m in re.findall(r"X\((\d+), (\d+), (\d+)\)", open(DEF).read())]
 # radix-2^29 limb count -> the 32-bit width class it serves
-CLASS_OF_S29 = {18: 16, 28: 24, 36: 32, 56: 48, 72: 64, 112: 96, 144: 128}
+CLASS_OF_S29 = {18: 16, 28: 24, 36: 32, 56: 48, 64: 48, 72: 64, 80: 64, 112: 96, 144: 128}
 
 
 def width_class(B, S):
