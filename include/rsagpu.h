@@ -108,7 +108,9 @@ int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *
  * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
  * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
  * operations inside rsa_ops_batch (separate plans: its buckets are smaller
- * and run side by side).
+ * and run side by side), 4 = the CRT half of the widest class of an
+ * rsa_ops_batch call with at least 16384 operations (the bucket that ends
+ * such a batch).
  * Inputs and outputs are 32-bit limbs whatever the radix.  Pure host query.
  */
 typedef struct {

@@ -375,8 +375,10 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
     for (int t = 0; t < nb; ++t) {
         const int b = order[t], cls = b / 2, kind = b % 2;
         const int width = kind == 0 ? class_width(cls) : class_width(cls) / 2;
+        // the ops-batch plans; a bulk batch's widest CRT bucket, which ends it, its own
+        const int pkind = (kind == 1 && t == 0 && nops >= kBulkOps) ? 4 : kind + 2;
         Resolved r;
-        if (!resolve(width, kind + 2, &r)) return RSA_ELIMBS;         // the ops-batch plans
+        if (!resolve(width, pkind, &r)) return RSA_ELIMBS;
         int per = r.inst->blocks_per_cu(kind, r.w);
         if (per <= 0) per = 1;
         const int blocks = per * cus;

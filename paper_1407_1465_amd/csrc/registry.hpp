@@ -34,6 +34,9 @@ struct Resolved {
     int w;
 };
 bool resolve(int limbs, int kind, Resolved *r);
+// rsa_ops_batch calls of at least this many operations take the kind-4 plan
+// for the CRT bucket of their widest class.
+static const size_t kBulkOps = 16384;
 
 // Processing order of a plain CRT batch that puts messages under the same key
 // next to each other (device array of count indices in stream-ordered

@@ -51,11 +51,14 @@ struct Plan {
 // Kinds 2 and 3 are the same operations inside rsa_ops_batch, whose buckets
 // are usually far smaller than a plain batch and run side by side: there a
 // narrower group (more waves per operation) and a smaller LDS footprint (room
-// for the other buckets' waves) pay off.  For 4096-bit CRT halves, 16
-// lanes (S = 80) shorten one operation, which a bulk mixed batch waits for
-// at its end (11% less time), but cost 64% more instructions per operation,
-// which a loaded server pays in latency (p50 +18%); the default keeps 8.
-static const int kKinds = 4;
+// for the other buckets' waves) pay off.  Kind 4 is the CRT half of the
+// widest class of a bulk ops batch (rsa_ops_batch with at least
+// kBulkOps operations), whose end waits for that bucket's last operations:
+// for 4096-bit keys 16 lanes (S = 80) shorten one operation (a mixed batch
+// of 32768 takes 11% less time) but cost 64% more instructions per
+// operation, which a loaded server's smaller batches pay in latency (p50
+// +18%), so kind 3 keeps 8.
+static const int kKinds = 5;
 static const Plan kDefault[kKinds][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 4},
@@ -66,6 +69,8 @@ static const Plan kDefault[kKinds][kNumClasses] = {
      {29, 4, 4}, {29, 8, 4}, {29, 16, 3}},
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
      {29, 8, 5}, {29, 16, 4}, {29, 16, 3}},
+    {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
+     {29, 16, 4}, {29, 16, 4}, {29, 16, 3}},
 };
 
 static int pack(const Plan &p) { return p.B << 16 | p.G << 8 | p.w; }

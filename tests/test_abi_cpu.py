@@ -84,8 +84,8 @@ def test_plans_are_consistent():
 
 
 def test_ops_batch_plans_are_separate():
-    """Kinds 2 and 3 (operations inside rsa_ops_batch) have their own plans:
-    overriding one leaves the plain-call plan (kinds 0 and 1) alone."""
+    """Kinds 2, 3 and 4 (operations inside rsa_ops_batch) have their own
+    plans: overriding one leaves the plain-call plan (kinds 0 and 1) alone."""
     from paper_1407_1465_amd import rsagpu
     plain = rsagpu.get_plan(32, 1)
     try:
@@ -98,7 +98,12 @@ def test_ops_batch_plans_are_separate():
     finally:
         rsagpu.set_plan(32, 3, 0, 0, 0)
         rsagpu.set_plan(64, 2, 0, 0, 0)
-    for kind in (-1, 4):
+    # kind 4: the widest CRT bucket of a bulk ops batch; 4096-bit halves on
+    # 16 lanes there (S = 80), on 8 in other ops batches
+    p4, p3 = rsagpu.get_plan(64, 4), rsagpu.get_plan(64, 3)
+    assert (p4.radix_bits, p4.padded_limbs, p4.lanes_per_op) == (29, 80, 16)
+    assert p3.lanes_per_op == 8
+    for kind in (-1, 5):
         with pytest.raises(Exception):
             rsagpu.get_plan(32, kind)
         with pytest.raises(Exception):
