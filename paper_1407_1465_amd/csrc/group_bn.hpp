@@ -104,6 +104,24 @@ __device__ __forceinline__ uint32_t grp_bcast0(uint32_t v)
     } else return (uint32_t)__shfl((int)v, 0, G);
 }
 
+// grp_bcast0(v) & mask, with the mask applied right after the first
+// (full-write) lane move so that the two fold into one DPP-modified AND
+// (mask in a VGPR); the later bank-masked moves copy the masked value.
+template <int G>
+__device__ __forceinline__ uint32_t grp_bcast0_and(uint32_t v, uint32_t mask)
+{
+    if constexpr (G == 1) return v & mask;
+    else if constexpr (G == 2 || G == 4) return grp_bcast0<G>(v) & mask;
+    else if constexpr (G == 8) {
+        const uint32_t q = dpp0<DPP_QP_0000>(v) & mask;
+        return dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);
+    } else if constexpr (G == 16) {
+        uint32_t q = dpp0<DPP_QP_0000>(v) & mask;
+        q = dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);
+        return dpp<DPP_ROW_SHR8, 0xF, 0xC>(q, q);
+    } else return grp_bcast0<G>(v) & mask;
+}
+
 // Value of lane K of this lane's group (G = 1, 2 or 4: at most one DPP quad
 // permute).
 template <int G, int K>
@@ -114,6 +132,11 @@ __device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
     else if constexpr (G == 2) return dpp0<K == 0 ? DPP_QP_0022 : DPP_QP_1133>(v);
     else return dpp0<K * 0x55>(v);                    // quad_perm [K, K, K, K]
 }
+
+// grp_rot_down(v) & mask with the mask folded into the row shift for 8 and
+// 16 lanes (the same lane-0-is-zero condition as grp_rot_down).
+template <int G>
+__device__ __forceinline__ uint32_t grp_rot_down_and(uint32_t v, uint32_t mask);
 
 // Lane r receives lane (r+1) mod G of its group.  Used where the group's
 // lane 0 holds zero, so the top lane receives zero (groups of 8 need an
@@ -131,6 +154,19 @@ __device__ __forceinline__ uint32_t grp_rot_down(uint32_t v)
     else {
         const uint32_t u = (uint32_t)__shfl_down((int)v, 1, G);
         return (lane_id() & (G - 1)) == G - 1 ? 0u : u;
+    }
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t grp_rot_down_and(uint32_t v, uint32_t mask)
+{
+    if constexpr (G == 8) {
+        const uint32_t u = dpp0<DPP_ROW_SHL1>(v) & mask;
+        return (lane_id() & 7) == 7 ? 0u : u;
+    } else if constexpr (G == 16) {
+        return dpp0<DPP_ROW_SHL1>(v) & mask;
+    } else {
+        return grp_rot_down<G>(v) & mask;
     }
 }
 

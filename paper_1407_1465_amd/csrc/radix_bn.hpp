@@ -234,12 +234,12 @@ __device__ __forceinline__ void rcios_reduce(uint64_t (&acc)[S / G], int k, cons
     // The masks follow the lane moves so that each pair folds into one
     // DPP-modified AND.
     const uint32_t Mv = vgpr_const(M);
-    const uint32_t m = grp_bcast0<G>((uint32_t)acc[p0] * n0inv) & Mv;
+    const uint32_t m = grp_bcast0_and<G>((uint32_t)acc[p0] * n0inv, Mv);
 #pragma unroll
     for (int j = 0; j < L; ++j) acc[(j + k) % L] += (uint64_t)m * n[j];
     acc[p1] += acc[p0] >> B;
     // the group's lane 0 holds zero in its low B bits here
-    acc[p0] = grp_rot_down<G>((uint32_t)acc[p0]) & Mv;
+    acc[p0] = grp_rot_down_and<G>((uint32_t)acc[p0], Mv);
 }
 
 // The L CIOS steps of one block: multiplier limbs bv[0 .. L) (already
