@@ -16,7 +16,9 @@ line carries
                 over the kernel's mean launch time from HIP events recorded
                 on the stream it runs on;
   cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) timed on a bounded
-                sample of the same messages on the host's cores.
+                sample of the same messages on the host's cores;
+  latency_ms:   p50 and p99 of the per-step (whole-batch) time over the
+                timed steps.
 
 Other workloads (--workload): rsa64, rsa1024 (full-d decryption, no CRT),
 enc2048 (e = 65537 encryption of the default batch), mixed (32768 operations
@@ -121,19 +123,29 @@ def modexp_products(key, e: int, plan) -> int:
     return exp_products(e, plan, key.limbs)
 
 
-def timed(fn, steps, warmup, torch):
+def timed(fn, steps, warmup, torch, per_step=None):
+    """Mean ms per step over `steps` back-to-back steps (HIP events on the
+    launch stream); per_step, if a list, receives each step's ms."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     wall0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(steps):
+    evs[0].record(stream)
+    for i in range(steps):
         fn()
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / steps, time.perf_counter() - wall0
+    if per_step is not None:
+        per_step.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
+    return evs[0].elapsed_time(evs[-1]) / steps, time.perf_counter() - wall0
+
+
+def percentile(xs, q):
+    """q-th percentile (nearest rank) of a non-empty list."""
+    ys = sorted(xs)
+    return ys[min(len(ys) - 1, max(0, int(-(-q * len(ys) // 100)) - 1))]
 
 
 # Sources the plain exponentiation and CRT kernels are compiled from (device
@@ -246,8 +258,12 @@ def main():
             p, q, dp, dq, qi = (dev(tab(wl, a, h)) for a in ("p", "q", "dp", "dq", "qinv"))
             out = torch.empty_like(c)
             plan = rsagpu.get_plan(h, 1)
+            steps_ms = []
             ms, wall = timed(lambda: rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out), args.steps, args.warmup,
-                             torch)
+                             torch, steps_ms)
+            # latency of one whole batch (steps back to back on the stream)
+            line["latency_ms"] = {"p50": percentile(steps_ms, 50), "p99": percentile(steps_ms, 99),
+                                  "of": "one batch of %d decryptions" % count}
             # round trip on a spread of elements before reporting
             idx = torch.arange(0, count, max(1, count // 64), device="cuda")
             back = rsagpu.modexp(out[idx].contiguous(), dev(e_h)[idx].contiguous(), dev(n_h)[idx].contiguous())
