@@ -216,8 +216,8 @@ def main():
                          "dispatch for hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(operations are independent; see the sharding note in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (operations are independent; "
+              "a batch would shard by contiguous ranges with no exchange step)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -45,7 +45,7 @@ def _draw_candidates(rng: W.SplitMix64, bits: int, e: int, count: int) -> List[C
     return out
 
 
-def _small_verdict(c: int):
+def _trial_division(c: int):
     """is_probable_prime's trial division by the first 40 primes: True/False
     when it decides, None when Miller-Rabin must."""
     for p in W._SMALL[:40]:
@@ -82,7 +82,6 @@ def miller_rabin_gpu(pairs: Sequence[Tuple[int, int]], limbs: int, rsagpu, torch
     ok = [v == 1 or v == c - 1 for v, c in zip(xs, cs)]
     todo = [i for i in range(len(cs)) if not ok[i] and rs[i] > 1]
     step = 1
-    two = None
     while todo:
         sel = torch.tensor(todo, dtype=torch.long, device="cuda")
         two = dev([2] * len(todo))
@@ -118,29 +117,29 @@ def make_keys_gpu(bits: int, seed: int, count: int, e: int = 65537, chunk: int =
         cands = {j: _draw_candidates(rngs[j], half, e, chunk) for j in pending}
         # first round for every candidate, the remaining rounds for those that pass it
         first = [(j, k) for j in pending for k in range(len(cands[j]))]
-        verdict = {}
+        passed = {}
         need_mr = []
         for j, k in first:
             c = cands[j][k][0]
-            v = _small_verdict(c)
+            v = _trial_division(c)
             if v is None:
                 need_mr.append((j, k))
             else:
-                verdict[(j, k)] = v
+                passed[(j, k)] = v
         r1 = miller_rabin_gpu([(cands[j][k][0], cands[j][k][1][0]) for j, k in need_mr], limbs, rsagpu, torch)
         rest = []
         for (j, k), ok in zip(need_mr, r1):
             if ok:
                 rest.extend(((j, k), a) for a in cands[j][k][1][1:])
-            verdict[(j, k)] = ok
+            passed[(j, k)] = ok
         r2 = miller_rabin_gpu([(cands[j][k][0], a) for (j, k), a in rest], limbs, rsagpu, torch)
         for ((j, k), _), ok in zip(rest, r2):
-            verdict[(j, k)] = verdict[(j, k)] and ok
+            passed[(j, k)] = passed[(j, k)] and ok
         still = []
         for j in pending:
             for k in range(len(cands[j])):
                 c = cands[j][k][0]
-                if len(found[j]) < 2 and verdict[(j, k)] and c not in found[j]:
+                if len(found[j]) < 2 and passed[(j, k)] and c not in found[j]:
                     found[j].append(c)
             if len(found[j]) < 2:
                 still.append(j)
