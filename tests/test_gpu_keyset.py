@@ -169,6 +169,10 @@ def test_workload_mixed_sizes_full():
     assert rsagpu.device_errors() == 0
     rng = np.random.default_rng(9)
     sample = rng.choice(len(w.kinds), 40, replace=False)
+    # plus CRT decryptions of the widest keys (the bulk batch's own plan)
+    widest = max(k.limbs for k in w.keys)
+    crt_w = [i for i in range(len(w.kinds)) if w.kinds[i] == 1 and w.keys[w.key_ids[i]].limbs == widest]
+    sample = np.unique(np.concatenate([sample, np.array(crt_w[:4] + crt_w[-2:])]))
     want = oracle_ops(w.keys, w.kinds[sample], w.key_ids[sample], w.in_offs[sample], w.in_pool)
     for j, i in enumerate(sample):
         L = w.keys[w.key_ids[i]].limbs
