@@ -118,9 +118,10 @@ struct rsa_keyset {
     unsigned class_mask;            // width classes present
     std::mutex mu;
     // fork/join of the per-bucket kernels (created on first use)
-    // one per hardware queue of a process (HIP's default of 4): more
-    // streams would share queues and serialise buckets behind each other
-    static const int kStreams = 4;
+    // with the caller's stream, one per hardware queue of a process (HIP's
+    // default of 4): more streams would share queues and serialise buckets
+    // behind each other
+    static const int kStreams = 3;
     hipStream_t streams[kStreams];
     hipEvent_t fork;
     hipEvent_t done[2 * 16];
@@ -364,14 +365,15 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
     if ((e = hipEventRecord(ks->fork, stream)) != hipSuccess) return status_of(e);
     // Bucket order and streams: the CRT buckets of the widest classes are the
     // longest (their operations are long dependency chains that a bucket's
-    // waves cannot shorten), so each of them gets a stream of its own; the
-    // remaining buckets (narrower CRT classes, then all encryptions, widest
-    // first) follow each other on the last stream, beside them.
+    // waves cannot shorten), so each of them gets a keyset stream of its own;
+    // the remaining buckets (narrower CRT classes, then all encryptions,
+    // widest first) follow each other on the caller's stream, beside them,
+    // which then waits for the keyset streams.
     int order[kMaxBuckets], nb = 0;
     for (int kind = 1; kind >= 0; --kind)
         for (int cls = num_classes() - 1; cls >= 0; --cls)
             if (mask & (1u << cls)) order[nb++] = cls * 2 + kind;
-    int used = 0;
+    int forked = 0;
     for (int t = 0; t < nb; ++t) {
         const int b = order[t], cls = b / 2, kind = b % 2;
         const int width = kind == 0 ? class_width(cls) : class_width(cls) / 2;
@@ -382,17 +384,19 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         int per = r.inst->blocks_per_cu(kind, r.w);
         if (per <= 0) per = 1;
         const int blocks = per * cus;
-        const int si = (kind == 1 && t < rsa_keyset::kStreams - 1) ? t : rsa_keyset::kStreams - 1;
-        hipStream_t s = ks->streams[si];
-        if ((e = hipStreamWaitEvent(s, ks->fork, 0)) != hipSuccess) return status_of(e);
+        const bool fork = kind == 1 && t < rsa_keyset::kStreams;
+        hipStream_t s = fork ? ks->streams[t] : stream;
+        if (fork && (e = hipStreamWaitEvent(s, ks->fork, 0)) != hipSuccess) return status_of(e);
         const ops_launcher fn = kind == 0 ? r.inst->ops_enc : r.inst->ops_crt;
         e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b, counters + b,
                in_pool, out_pool, r.w, blocks, s);
         if (e != hipSuccess) return status_of(e);
-        hipEvent_t done = ks->done[used % (2 * 16)];
-        if ((e = hipEventRecord(done, s)) != hipSuccess) return status_of(e);
-        if ((e = hipStreamWaitEvent(stream, done, 0)) != hipSuccess) return status_of(e);
-        ++used;
+        if (fork) {
+            if ((e = hipEventRecord(ks->done[t], s)) != hipSuccess) return status_of(e);
+            ++forked;
+        }
     }
+    for (int t = 0; t < forked; ++t)
+        if ((e = hipStreamWaitEvent(stream, ks->done[t], 0)) != hipSuccess) return status_of(e);
     return RSA_OK;
 }
