@@ -389,7 +389,7 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         if (fork && (e = hipStreamWaitEvent(s, ks->fork, 0)) != hipSuccess) return status_of(e);
         const ops_launcher fn = kind == 0 ? r.inst->ops_enc : r.inst->ops_crt;
         e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b, counters + b,
-               in_pool, out_pool, r.w, blocks, s);
+               in_pool, out_pool, r.w, blocks, pkind == 4 ? 1 : 0, s);
         if (e != hipSuccess) return status_of(e);
         if (fork) {
             if ((e = hipEventRecord(ks->done[t], s)) != hipSuccess) return status_of(e);

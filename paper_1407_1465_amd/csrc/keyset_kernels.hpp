@@ -118,7 +118,7 @@ template <int S, int G, int B>
 __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
                                                 const unsigned *__restrict__ list, const unsigned *count_p,
                                                 unsigned *counter, const uint32_t *__restrict__ in_pool,
-                                                uint32_t *out_pool, int w)
+                                                uint32_t *out_pool, int w, int urgent)
 {
     using Ar = Arith<S, G, B>;
     constexpr int L = S / G, NG = 64 / G;
@@ -126,6 +126,7 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
     const int g = grp_index<G>();
     const unsigned count = *count_p;
+    if (urgent) __builtin_amdgcn_s_setprio(2);
     for (;;) {
         const unsigned base = claim(counter, NG);
         if (base >= count) break;                     // wave-uniform exit
@@ -161,7 +162,7 @@ template <int H, int G, int B>
 __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
                                                  const unsigned *__restrict__ list, const unsigned *count_p,
                                                  unsigned *counter, const uint32_t *__restrict__ in_pool,
-                                                 uint32_t *out_pool, int w)
+                                                 uint32_t *out_pool, int w, int urgent)
 {
     using Ar = Arith<H, G, B>;
     using Ly = Layout<H, G>;
@@ -174,6 +175,7 @@ __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys
     uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + region;     // wave 1's region
     const int g = grp_index<G>(), r = grp_lane<G>();
     const unsigned count = *count_p;
+    if (urgent) __builtin_amdgcn_s_setprio(2);
     for (;;) {
         // Wave 0 reaches this barrier after Garner has read the previous
         // chunk's m_q, and wave 1 reads `chunk` before the barrier below:

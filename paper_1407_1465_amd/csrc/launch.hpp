@@ -24,10 +24,11 @@ struct OpDesc;
 typedef hipError_t (*setup_launcher)(const uint32_t *const *mods, const uint32_t *const *mults, const int *words,
                                      ModConsts *outs, int count, hipStream_t stream);
 // Persistent bucket kernel: `blocks` workgroups claim operations until the
-// bucket (list, *count) is exhausted.
+// bucket (list, *count) is exhausted; with `urgent` its waves issue ahead of
+// other kernels' waves on a shared SIMD (the bucket that ends a batch).
 typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const unsigned *list,
                                    const unsigned *count, unsigned *counter, const uint32_t *in_pool,
-                                   uint32_t *out_pool, int w, int blocks, hipStream_t stream);
+                                   uint32_t *out_pool, int w, int blocks, int urgent, hipStream_t stream);
 // Workgroups of an ops kernel resident per CU at window w (occupancy query).
 typedef int (*ops_occupancy)(int kind, int w);
 
@@ -79,12 +80,12 @@ hipError_t launch_setup(const uint32_t *const *mods, const uint32_t *const *mult
 template <int S, int G, int B>
 hipError_t launch_ops_enc(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
-                          hipStream_t stream);
+                          int urgent, hipStream_t stream);
 
 template <int S, int G, int B>
 hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
-                          hipStream_t stream);
+                          int urgent, hipStream_t stream);
 
 template <int S, int G, int B>
 int ops_blocks_per_cu(int kind, int w);

@@ -43,20 +43,20 @@ hipError_t launch_setup(const uint32_t *const *mods, const uint32_t *const *mult
 template <int S, int G, int B>
 hipError_t launch_ops_enc(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
-                          hipStream_t stream)
+                          int urgent, hipStream_t stream)
 {
     hipLaunchKernelGGL((k_ops_enc<S, G, B>), dim3(blocks), dim3(64), lds_bytes_for(S, G, B, w), stream, keys, ops,
-                       list, count, counter, in_pool, out_pool, w);
+                       list, count, counter, in_pool, out_pool, w, urgent);
     return hipGetLastError();
 }
 
 template <int S, int G, int B>
 hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
-                          hipStream_t stream)
+                          int urgent, hipStream_t stream)
 {
     hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(128), 2 * lds_bytes_for(S, G, B, w), stream, keys,
-                       ops, list, count, counter, in_pool, out_pool, w);
+                       ops, list, count, counter, in_pool, out_pool, w, urgent);
     return hipGetLastError();
 }
 
@@ -87,8 +87,8 @@ int ops_blocks_per_cu(int kind, int w)
                                                          hipStream_t);                                      \
     template hipError_t rsagpu::launch_ops_enc<S_, G_, B_>(                                                 \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
-        const uint32_t *, uint32_t *, int, int, hipStream_t);                                               \
+        const uint32_t *, uint32_t *, int, int, int, hipStream_t);                                          \
     template hipError_t rsagpu::launch_ops_crt<S_, G_, B_>(                                                 \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
-        const uint32_t *, uint32_t *, int, int, hipStream_t);                                               \
+        const uint32_t *, uint32_t *, int, int, int, hipStream_t);                                          \
     template int rsagpu::ops_blocks_per_cu<S_, G_, B_>(int, int);
