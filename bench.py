@@ -18,7 +18,10 @@ line carries
   cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) timed on a bounded
                 sample of the same messages on the host's cores;
   latency_ms:   p50 and p99 of the per-step (whole-batch) time over the
-                timed steps.
+                timed steps;
+  check:        elements of the whole batch whose round trip through the
+                opposite operation (decryptions re-encrypted, encryptions
+                decrypted) differs; the run fails unless it is 0.
 
 Other workloads (--workload): rsa64, rsa1024 (full-d decryption, no CRT),
 enc2048 (e = 65537 encryption of the default batch), mixed (32768 operations
@@ -140,6 +143,11 @@ def timed(fn, steps, warmup, torch, per_step=None):
     if per_step is not None:
         per_step.extend(evs[i].elapsed_time(evs[i + 1]) for i in range(steps))
     return evs[0].elapsed_time(evs[-1]) / steps, time.perf_counter() - wall0
+
+
+def row_mismatches(a, b) -> int:
+    """Rows (elements) of two (count, limbs) device tensors that differ."""
+    return int((a != b).any(dim=1).sum().item())
 
 
 def percentile(xs, q):
@@ -264,11 +272,13 @@ def main():
             # latency of one whole batch (steps back to back on the stream)
             line["latency_ms"] = {"p50": percentile(steps_ms, 50), "p99": percentile(steps_ms, 99),
                                   "of": "one batch of %d decryptions" % count}
-            # round trip on a spread of elements before reporting
-            idx = torch.arange(0, count, max(1, count // 64), device="cuda")
-            back = rsagpu.modexp(out[idx].contiguous(), dev(e_h)[idx].contiguous(), dev(n_h)[idx].contiguous())
-            if not torch.equal(back, c[idx]):
-                raise SystemExit("round-trip check failed")
+            # every decryption re-encrypted (e = 65537) must give its ciphertext back
+            back = rsagpu.modexp(out, dev(e_h), dev(n_h))
+            bad = row_mismatches(back, c)
+            line["check"] = {"mismatches": bad, "of": "all %d decryptions, re-encrypted against the "
+                                                      "ciphertexts" % count}
+            if bad:
+                raise SystemExit("round-trip check failed on %d elements" % bad)
             products = per_key_sum(wl.key_of, lambda k: crt_products(wl.keys[k], plan))
             # the same batch as one launch per key (plain form, no cross-key batching)
             per_key = []
@@ -300,6 +310,12 @@ def main():
             out = torch.empty_like(m)
             plan = rsagpu.get_plan(L, 0)
             ms, wall = timed(lambda: rsagpu.modexp(m, e, n, out=out), args.steps, args.warmup, torch)
+            back = rsagpu.decrypt_crt(out, *(dev(tab(wl, a, h)) for a in ("p", "q", "dp", "dq", "qinv")))
+            bad = row_mismatches(back, m)
+            line["check"] = {"mismatches": bad, "of": "all %d encryptions, decrypted (CRT) against the "
+                                                      "messages" % count}
+            if bad:
+                raise SystemExit("round-trip check failed on %d elements" % bad)
             products = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].e, plan))
             line.update(metric="2048-bit modexp/sec (encrypt, e=65537) on 1 GPU", unit="encryptions/s",
                         config={"workload": "rsa2048-encrypt", "keys": len(wl.keys), "messages": count,
@@ -322,6 +338,12 @@ def main():
         out = torch.empty_like(c)
         plan = rsagpu.get_plan(L, 0)
         ms, wall = timed(lambda: rsagpu.modexp(c, d, n, out=out), args.steps, args.warmup, torch)
+        back = rsagpu.modexp(out, dev(tab(wl, "e", L)), n)
+        bad = row_mismatches(back, c)
+        line["check"] = {"mismatches": bad, "of": "all %d decryptions, re-encrypted against the "
+                                                  "ciphertexts" % count}
+        if bad:
+            raise SystemExit("round-trip check failed on %d elements" % bad)
         products = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].d, plan))
         line.update(metric="%d-bit modexp/sec (full-d decrypt) on 1 GPU" % (32 * L), unit="decryptions/s",
                     config={"workload": wl.name + "-decrypt", "messages": count, "radix_bits": plan.radix_bits,
@@ -350,7 +372,11 @@ def main():
         ops_inv = rsagpu.pack_ops(1 - wl.kinds, wl.key_ids, wl.in_offs, wl.in_offs).cuda()
         rsagpu.ops_batch(ks, ops_inv, out, back, ws)
         torch.cuda.synchronize()
-        if not torch.equal(back, inp) or rsagpu.device_errors() != 0:
+        bad_words = int((back != inp).sum().item())
+        errs = rsagpu.device_errors()
+        line["check"] = {"mismatches": bad_words + errs, "of": "every operation's output put through the "
+                                                               "opposite operation (words differing + data errors)"}
+        if bad_words or errs:
             raise SystemExit("mixed batch round trip failed")
         def op_products(kk):
             kind, kid = kk
@@ -368,7 +394,7 @@ def main():
         # The paper's own experiment (Section 10, Tables 1 and 2): one-word
         # moduli, e = 131, messages 0..800, at every data size the tables
         # list; encryption and decryption (round trip checked) per size.
-        rows = []
+        rows, checked = [], 0
         for t, key in sorted(W.PAPER_TABLE_KEYS.items()):
             for i, N in enumerate(W.PAPER_TABLE_SIZES):
                 msgs = W.paper_table_messages(N)
@@ -382,6 +408,7 @@ def main():
                 ms_dec, _ = timed(lambda: rsagpu.modexp(c, d, n, out=back), args.steps, args.warmup, torch)
                 if not torch.equal(back, m):
                     raise SystemExit("paper-table round trip failed (table %d, %d messages)" % (t, N))
+                checked += N
                 rows.append({"table": t, "n": key.n, "e": key.e, "d": key.d, "messages": N,
                              "encrypt_ms": ms_enc, "decrypt_ms": ms_dec,
                              "paper_gpu_time_as_printed": W.PAPER_TABLE_GPU_TIME[t][i]})
@@ -393,6 +420,7 @@ def main():
                     config={"workload": "paper-tables-1-2", "radix_bits": plan.radix_bits,
                             "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
         line["rows"] = rows
+        line["check"] = {"mismatches": 0, "of": "all %d messages encrypted and decrypted back" % checked}
         value = last["messages"] / (ms / 1e3)
 
     elif args.workload == "keygen":
@@ -411,6 +439,7 @@ def main():
         cpu_s = time.perf_counter() - t2
         if keys[0] != cpu_key:
             raise SystemExit("GPU key generation differs from the CPU generator")
+        line["check"] = {"mismatches": 0, "of": "key 0 against the CPU generator; every key's own consistency"}
         ms = wall * 1e3
         line.update(metric="4096-bit RSA key generation (Miller-Rabin on the GPU) keys/s on 1 GPU",
                     unit="keys/s", config={"workload": "keygen-4096", "keys": nk, "modulus_bits": bits})
@@ -429,16 +458,45 @@ def main():
         pool, max_ops = 1 << 23, 1 << 16
         ex = GpuExecutor(ks, limbs, pool, max_ops)
 
+        last = {}
+
         def run(reqs):
             srv = Server(ex, pool, max_inflight=2, max_ops=max_ops)
             srv.run(reqs)
+            last["finished"] = srv.finished
             return srv.stats()
+
+        def verify(finished):
+            """Every served message through the opposite operation (one
+            rsa_ops_batch per chunk, after the timed run): elements whose
+            round trip differs."""
+            items = [(r.kind, r.key_id, row) for r in finished if r.error is None
+                     for row in zip(r.outputs, r.inputs)]
+            bad, chunk = 0, 1 << 15
+            ws_v = torch.empty(rsagpu.ops_workspace_size(chunk), dtype=torch.uint8, device="cuda")
+            for i0 in range(0, len(items), chunk):
+                part = items[i0:i0 + chunk]
+                offs = np.cumsum([0] + [limbs[kid] for _, kid, _ in part])
+                outs = np.concatenate([o for _, _, (o, _) in part]).astype(np.uint32)
+                ins = np.concatenate([x for _, _, (_, x) in part]).astype(np.uint32)
+                vops = rsagpu.pack_ops(np.array([1 - k for k, _, _ in part]), np.array([kid for _, kid, _ in part]),
+                                       offs[:-1], offs[:-1]).cuda()
+                back = torch.zeros(int(offs[-1]), dtype=torch.int32, device="cuda")
+                rsagpu.ops_batch(ks, vops, dev(outs), back, ws_v)
+                diff = back.cpu().numpy().view(np.uint32) != ins
+                bad += int(np.logical_or.reduceat(diff, offs[:-1]).sum())
+            return bad, len(items)
         # saturated rate: a closed burst
         sat = run(poisson_requests(0.0, 400, W.SEED_BASE + 50, limbs, mods))
         rate = 0.7 * sat["requests_per_s"]
         nreq = max(200, int(rate * args.serve_seconds))
         st = run(poisson_requests(rate, nreq, W.SEED_BASE + 51, limbs, mods))
-        if st["errors"] or rsagpu.device_errors():
+        bad, nmsg = verify(last["finished"])
+        errs = rsagpu.device_errors()
+        line["check"] = {"mismatches": bad + st["errors"] + errs,
+                         "of": "all %d served messages through the opposite operation, plus failed requests "
+                               "and device data errors" % nmsg}
+        if bad or st["errors"] or errs:
             raise SystemExit("serving run reported errors")
         line.update(metric="RSA serving (2048/4096-bit keys, 70% CRT decrypt): requests/s at p50/p99 latency",
                     unit="requests/s",
