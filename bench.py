@@ -14,7 +14,8 @@ line carries
                 h(h+1)/2 + h^2 + h per squaring where the kernel squares
                 with one product per limb pair, plus the recombination)
                 over the kernel's mean launch time from HIP events recorded
-                on the stream it runs on;
+                on the stream it runs on (frac_squarings_as_products: the
+                same with every squaring counted at 2h^2 + h);
   cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) timed on a bounded
                 sample of the same messages on the host's cores;
   latency_ms:   p50 and p99 of the per-step (whole-batch) time over the
@@ -100,11 +101,13 @@ def symmetric_squarings(plan) -> bool:
     return plan.radix_bits == 29 and 3 * plan.limbs_per_lane <= 62
 
 
-def exp_products(e: int, plan, s: int) -> int:
+def exp_products(e: int, plan, s: int, general_squarings: bool = False) -> int:
     """Algorithmic 32x32-bit products of x^e mod n at s 32-bit limbs with
-    the plan's window."""
+    the plan's window (general_squarings: every squaring counted as a
+    general product, for comparison)."""
     sq, mul, tsize = sliding_window_counts(e, plan.window_bits)
-    per_sq = sqr_products(s) if symmetric_squarings(plan) else mont_products(s)
+    sym = symmetric_squarings(plan) and not general_squarings
+    per_sq = sqr_products(s) if sym else mont_products(s)
     return sq * per_sq + (mul + (tsize if tsize > 1 else 0)) * mont_products(s)
 
 
@@ -116,10 +119,11 @@ def per_key_sum(key_of, fn) -> int:
                                                              keys)).items())
 
 
-def crt_products(key, plan) -> int:
+def crt_products(key, plan, general_squarings: bool = False) -> int:
     """Two half exponentiations and Garner's product (h^2 more for m_q + h*q)."""
     h = key.limbs // 2
-    return exp_products(key.dp, plan, h) + exp_products(key.dq, plan, h) + mont_products(h) + h * h
+    return (exp_products(key.dp, plan, h, general_squarings) + exp_products(key.dq, plan, h, general_squarings) +
+            mont_products(h) + h * h)
 
 
 def modexp_products(key, e: int, plan) -> int:
@@ -299,6 +303,9 @@ def main():
                                 "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
             line["roofline"] = roofline(products, ms, "k_crt<%d,%d,%d>" % (plan.padded_limbs, plan.lanes_per_op,
                                                                            plan.radix_bits))
+            # the same fraction with every squaring counted as a general product
+            general = per_key_sum(wl.key_of, lambda k: crt_products(wl.keys[k], plan, True))
+            line["roofline"]["frac_squarings_as_products"] = general / (ms / 1e3) / INT32_MUL_PEAK
             if args.cpu_sample:
                 import oracle
                 cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32),
