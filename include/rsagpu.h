@@ -17,10 +17,12 @@
  *   - Work is enqueued on `stream` (NULL = the null stream) and is
  *     asynchronous: the call returns before the results exist.  No entry
  *     point synchronises the device except rsa_device_errors.
- *   - No entry point allocates device memory per call: operands and the
- *     window table of each exponentiation live in registers and LDS (the
- *     only device allocation is an 8-byte error counter made once per
- *     device, see rsa_init).
+ *   - Operands and the window table of each exponentiation live in
+ *     registers and LDS.  rsa_modexp_batch and rsa_ops_batch allocate no
+ *     device memory per call; rsa_decrypt_crt_batch takes its key-ordering
+ *     scratch from the device's memory pool, stream-ordered (see there);
+ *     rsa_autotune and rsa_keyset_create allocate their own buffers.  The
+ *     per-device state is an 8-byte error counter made once (rsa_init).
  *   - Host-checkable errors are returned before any HIP call.  Per-element
  *     data errors (an even or unit modulus, p <= q for CRT) write 0 to that
  *     element's output and increment a per-device counter that
@@ -203,7 +205,8 @@ size_t rsa_ops_workspace_size(size_t max_ops);
  * bound the pools: an operation whose kind, key id or ranges are invalid is
  * skipped and counted as a data error.  workspace: caller-owned device
  * memory of at least rsa_ops_workspace_size(nops) bytes; calls that overlap
- * in time must use different workspaces.  Asynchronous on `stream`.
+ * in time must use different workspaces.  nops < 2^32 (RSA_EINVAL beyond).
+ * Asynchronous on `stream`.
  */
 int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, const uint32_t *in_pool, size_t in_words,
                   uint32_t *out_pool, size_t out_words, void *workspace, size_t ws_bytes, hipStream_t stream);

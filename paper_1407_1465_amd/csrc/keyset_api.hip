@@ -317,6 +317,8 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
 {
     if (!ks) return RSA_EINVAL;
     if (nops == 0) return RSA_OK;
+    // operation indices and bucket counts are 32-bit on the device
+    if (nops > 0xffffffffull) return RSA_EINVAL;
     if (!ops || !in_pool || !out_pool || !workspace || ws_bytes < rsa_ops_workspace_size(nops)) return RSA_EINVAL;
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != ks->device) return RSA_EINVAL;
