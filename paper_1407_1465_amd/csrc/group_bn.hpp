@@ -58,7 +58,8 @@ __device__ __forceinline__ constexpr uint64_t top_lanes_mask()
 //
 // Groups of up to 16 lanes never straddle a DPP row, so the moves below are
 // DPP data movements (no LDS round trip): quad_perm for groups of 2 and 4,
-// row shifts with bank masks for 8 and 16.
+// row shifts with bank masks for 8 and 16, and for the broadcast of a 16-lane
+// group's lane 0 the row broadcast that CDNA3/4 DPP provides.
 
 template <int CTRL, int ROW_MASK = 0xF, int BANK_MASK = 0xF>
 __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v)
@@ -84,7 +85,7 @@ enum : int {
     DPP_ROW_SHL1 = 0x101,    // lane i <- lane i+1 within a row of 16
     DPP_ROW_SHR1 = 0x111,    // lane i <- lane i-1 within a row of 16
     DPP_ROW_SHR4 = 0x114,
-    DPP_ROW_SHR8 = 0x118,
+    DPP_ROW_NEWBCAST0 = 0x150,  // every lane of a row of 16 <- the row's lane 0
 };
 
 // Value of lane 0 of this lane's group.
@@ -97,11 +98,8 @@ __device__ __forceinline__ uint32_t grp_bcast0(uint32_t v)
     else if constexpr (G == 8) {
         const uint32_t q = dpp0<DPP_QP_0000>(v);
         return dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);           // banks 1, 3 take banks 0, 2
-    } else if constexpr (G == 16) {
-        uint32_t q = dpp0<DPP_QP_0000>(v);
-        q = dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);
-        return dpp<DPP_ROW_SHR8, 0xF, 0xC>(q, q);           // banks 2, 3 take banks 0, 1
-    } else return (uint32_t)__shfl((int)v, 0, G);
+    } else if constexpr (G == 16) return dpp0<DPP_ROW_NEWBCAST0>(v);
+    else return (uint32_t)__shfl((int)v, 0, G);
 }
 
 // grp_bcast0(v) & mask, with the mask applied right after the first
@@ -116,9 +114,7 @@ __device__ __forceinline__ uint32_t grp_bcast0_and(uint32_t v, uint32_t mask)
         const uint32_t q = dpp0<DPP_QP_0000>(v) & mask;
         return dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);
     } else if constexpr (G == 16) {
-        uint32_t q = dpp0<DPP_QP_0000>(v) & mask;
-        q = dpp<DPP_ROW_SHR4, 0xF, 0xA>(q, q);
-        return dpp<DPP_ROW_SHR8, 0xF, 0xC>(q, q);
+        return dpp0<DPP_ROW_NEWBCAST0>(v) & mask;
     } else return grp_bcast0<G>(v) & mask;
 }
 
