@@ -78,7 +78,6 @@ __global__ __launch_bounds__(64) void k_setup(const uint32_t *const *mods, const
                                               const int *words, ModConsts *outs, int count)
 {
     using Ar = Arith<S, G, B>;
-    using Ly = Layout<S, G>;
     constexpr int L = S / G, NG = 64 / G;
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
     const int g = grp_index<G>();
@@ -91,7 +90,7 @@ __global__ __launch_bounds__(64) void k_setup(const uint32_t *const *mods, const
     const bool valid = live && (n0 & 1u) && bl > 1;
     const uint32_t n0inv = Ar::n0inv(n0 | 1u);
     uint32_t one[L], r2[L], t[L];
-    mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds, lds + Ly::WORDS);
+    mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds);
     const ModConsts oc = live ? outs[i] : ModConsts{nullptr, nullptr, nullptr, nullptr};
     store_raw<S, G>(oc.one, one, live);
     store_raw<S, G>(oc.r2, r2, live);
@@ -140,7 +139,7 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
         Ar::load(x, in_pool + op.in_off, k.words, 0, live);
         const uint32_t n0inv = Ar::n0inv(grp_bcast0<G>(n[0]) | 1u);
         if constexpr (OWN) {
-            mont_setup<S, G, B>(one, r2, n, n0inv, live, lds, lds + Layout<S, G>::WORDS);
+            mont_setup<S, G, B>(one, r2, n, n0inv, live, lds);
         } else {
             load_raw<S, G>(one, mc.one, live);
             load_raw<S, G>(r2, mc.r2, live);
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys
         // xt = c * R mod m = c_lo * R^2 * R^-1 + c_hi * R^3 * R^-1  (c = c_lo + c_hi * R)
         uint32_t xt[L], t2[L], r2[L];
         if constexpr (OWN) {
-            mont_setup<H, G, B>(one, r2, n, n0inv, live, lds, lds + Ly::WORDS);
+            mont_setup<H, G, B>(one, r2, n, n0inv, live, lds);
             mont_mul_reg<H, G, B>(xt, clo, r2, lds, n, n0inv);
             mont_mul_reg<H, G, B>(rk, r2, r2, lds, n, n0inv);        // R^3 mod m
             mont_mul_reg<H, G, B>(t2, chi, rk, lds, n, n0inv);

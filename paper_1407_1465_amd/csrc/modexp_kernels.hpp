@@ -213,15 +213,17 @@ __device__ __forceinline__ void mont_sqr(uint32_t (&A)[S / G], uint32_t *abuf, c
 
 // Montgomery constants of an odd modulus n > 1 in radix 2^B, R = 2^(B*S):
 //   one = R mod n:   2^(bitlen(n)-1) doubled B*S - bitlen(n) + 1 times;
-//   r2 = R^2 mod n:  X = 2R mod n, then left-to-right over the bits of B*S
-//                    below the top one: X <- X*X/R (exponent of 2 doubles),
-//                    and X <- X*(2R)/R when the bit is set (exponent + 1);
-//                    X = R * 2^e mod n throughout, ending at e = B*S.
-// `aux` is an LDS operand buffer other than `abuf`.
+//   r2 = R^2 mod n:  X = R * 2^e mod n throughout, ending at e = B*S: R
+//                    doubled e0 times, e0 the top five bits of B*S, then
+//                    left-to-right over its remaining bits X <- X*X/R (e
+//                    doubles) and one more doubling where the bit is set
+//                    (e + 1).  A doubling costs a few instructions per limb,
+//                    a Montgomery squaring hundreds, so the first squarings
+//                    of the ladder (e = 1, 2, 4, ...) are doublings instead.
 template <int S, int G, int B>
 __device__ __forceinline__ void mont_setup(uint32_t (&one)[S / G], uint32_t (&r2)[S / G],
                                            const uint32_t (&n)[S / G], uint32_t n0inv, bool valid,
-                                           uint32_t *abuf, uint32_t *aux)
+                                           uint32_t *abuf)
 {
     using A = Arith<S, G, B>;
     constexpr int L = S / G;
@@ -246,19 +248,15 @@ __device__ __forceinline__ void mont_setup(uint32_t (&one)[S / G], uint32_t (&r2
 #pragma unroll
         for (int k = 0; k < L; ++k) one[k] = act ? y[k] : one[k];
     }
-    uint32_t x2[L];
-#pragma unroll
-    for (int k = 0; k < L; ++k) x2[k] = one[k];
-    A::dbl_mod(x2, n);                                   // 2R mod n
-    lds_sync();
-    lds_put<S, G>(aux, x2);
-#pragma unroll
-    for (int k = 0; k < L; ++k) r2[k] = x2[k];
     constexpr int E = B * S;
     constexpr int TOP = 31 - __builtin_clz((unsigned)E);
-    for (int bit = TOP - 1; bit >= 0; --bit) {
+    constexpr int SH = TOP > 4 ? TOP - 4 : 0;          // E >> SH in [16, 32)
+#pragma unroll
+    for (int k = 0; k < L; ++k) r2[k] = one[k];
+    for (int t = 0; t < (E >> SH); ++t) A::dbl_mod(r2, n);
+    for (int bit = SH - 1; bit >= 0; --bit) {
         mont_sqr<S, G, B>(r2, abuf, n, n0inv);
-        if ((E >> bit) & 1) A::mont_mul(r2, r2, aux, n, n0inv);
+        if ((E >> bit) & 1) A::dbl_mod(r2, n);
     }
 }
 
@@ -537,7 +535,6 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_modexp(const uint3
                                                unsigned long long *errs)
 {
     using Ar = Arith<S, G, B>;
-    using Ly = Layout<S, G>;
     constexpr int L = S / G, NG = 64 / G;
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds);
     const int g = grp_index<G>(), r = grp_lane<G>();
@@ -554,7 +551,7 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_modexp(const uint3
     const uint32_t n0inv = Ar::n0inv(n0 | 1u);
 
     uint32_t one[L], r2[L], xt[L], A[L];
-    mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds, lds + Ly::WORDS);
+    mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds);
     mont_mul_reg<S, G, B>(xt, x, r2, lds, n, n0inv);
     group_modexp<S, G, B>(A, xt, exp + off, limbs, valid, n, n0inv, one, lds, w);
     from_mont<S, G, B>(A, lds, n, n0inv);
@@ -615,7 +612,7 @@ __global__ __launch_bounds__(128) void k_crt(const uint32_t *__restrict__ c, con
     const uint32_t n0inv = Ar::n0inv(n0 | 1u);
 
     uint32_t one[L], r2[L], r3[L];
-    mont_setup<H, G, B>(one, r2, n, n0inv, valid, lds, lds + Ly::WORDS);
+    mont_setup<H, G, B>(one, r2, n, n0inv, valid, lds);
     mont_mul_reg<H, G, B>(r3, r2, r2, lds, n, n0inv);        // R^3 mod n
 
     // xt = c * R mod n = c_lo * R + c_hi * R * R  (c = c_lo + c_hi * R)
