@@ -374,6 +374,17 @@ constexpr bool rsqr_fits()
 // take that pair in their own block).  Every column still receives all its
 // terms no later than its drain, so m and the result are those of the
 // general product rcios_block computes with b = a; a2 holds 2a.
+//
+// The j == k multiplier is taken from the doubled limb b2 = 2 * limb < 2^31
+// (limbs, redundant ones included, are below 2^30) by one bit-field
+// extract whose per-lane offset and width are fixed for the block: b2 above
+// lane Q (offset 0, width 31), b2 / 2 -- lane Q's own limb -- in lane Q
+// (offset 1, width 31), 0 below (width 0).
+__device__ __forceinline__ uint32_t diag_mult(uint32_t b2, uint32_t off, uint32_t wid)
+{
+    return __builtin_amdgcn_ubfe(b2, off, wid);
+}
+
 template <int S, int G, int B, int Q>
 struct RSqrBlocks {
     static __device__ __forceinline__ void run(uint64_t (&acc)[S / G], const uint32_t (&a)[S / G],
@@ -383,10 +394,11 @@ struct RSqrBlocks {
         if constexpr (Q < G) {
             constexpr int L = S / G;
             const int r = grp_lane<G>();
+            const uint32_t off = r == Q ? 1u : 0u, wid = r >= Q ? 31u : 0u;
 #pragma unroll
             for (int k = 0; k < L; ++k) {
                 const uint32_t b2 = grp_bcast_lane<G, Q>(a2[k]);
-                const uint32_t bd = r > Q ? b2 : (r == Q ? a[k] : 0u);
+                const uint32_t bd = diag_mult(b2, off, wid);
                 acc[(2 * k) % L] += (uint64_t)a[k] * bd;
 #pragma unroll
                 for (int j = k + 1; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * b2;
@@ -439,11 +451,11 @@ __device__ __forceinline__ void rmont_sqr(uint32_t (&r)[S / G], const uint32_t (
 #pragma unroll
             for (int u = 0; u < V; ++u) bv[k + u] = pv[u];
         }
-        const bool above = lane > q, own = lane == q;
+        const uint32_t off = lane == q ? 1u : 0u, wid = lane >= q ? 31u : 0u;
 #pragma unroll
         for (int k = 0; k < L; ++k) {
             const uint32_t b2 = bv[k] << 1;
-            const uint32_t bd = above ? b2 : (own ? a[k] : 0u);
+            const uint32_t bd = diag_mult(b2, off, wid);
             acc[(2 * k) % L] += (uint64_t)a[k] * bd;
 #pragma unroll
             for (int j = k + 1; j < L; ++j) acc[(j + k) % L] += (uint64_t)a[j] * b2;

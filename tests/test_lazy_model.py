@@ -110,11 +110,19 @@ class Model:
         return acc
 
 
+def ubfe(x, off, wid):
+    """The 32-bit unsigned bit-field extract of the AMD ISA (v_bfe_u32):
+    offset and width use their low five bits."""
+    return (x >> (off & 31)) & ((1 << (wid & 31)) - 1)
+
+
 def sqr_loop(md, a, n):
     """The symmetric squaring's S steps (rmont_sqr_regs): step k of block q
     runs registers j >= k only; j > k multiply by 2a[qL+k] in every lane,
     j == k squares lane q's own limb, doubles the pair in lanes above q and
-    adds nothing in lanes below q.  Returns (accumulators, multiplier slots
+    adds nothing in lanes below q -- the kernel takes that multiplier out of
+    the doubled limb with one bit-field extract (offset 1 in lane q, width 31
+    from lane q up, width 0 below).  Returns (accumulators, multiplier slots
     run per lane)."""
     S, G, L, B, M = md.S, md.G, md.L, md.B, md.M
     ninv = n0inv_of(n[0], B)
@@ -123,15 +131,17 @@ def sqr_loop(md, a, n):
     for q in range(G):
         for k in range(L):
             b = a[q * L + k]
+            b2 = 2 * b
+            assert b2 < 1 << 31, "doubled limb must fit the extract's 31-bit width"
             for j in range(k, L):
                 slots += 1
                 for g in range(G):
-                    if j > k or g > q:
-                        f = 2 * b
-                    elif g == q:
-                        f = a[g * L + j]
+                    if j > k:
+                        f = b2
                     else:
-                        f = 0
+                        f = ubfe(b2, 1 if g == q else 0, 31 if g >= q else 0)
+                        # what the extract must give: lane q's own limb, the doubled pair, or nothing
+                        assert f == (a[g * L + j] if g == q else (b2 if g > q else 0))
                     md._add(acc, g, (j + k) % L, a[g * L + j] * f)
             p0, p1 = k % L, (k + 1) % L
             m = (((acc[0][p0] & 0xFFFFFFFF) * ninv) & 0xFFFFFFFF) & M
