@@ -85,7 +85,7 @@ enum : int {
     DPP_ROW_SHL1 = 0x101,    // lane i <- lane i+1 within a row of 16
     DPP_ROW_SHR1 = 0x111,    // lane i <- lane i-1 within a row of 16
     DPP_ROW_SHR4 = 0x114,
-    DPP_ROW_NEWBCAST0 = 0x150,  // every lane of a row of 16 <- the row's lane 0
+    DPP_ROW_NEWBCAST0 = 0x150,  // every lane of a row of 16 <- the row's lane 0 (+K: lane K)
 };
 
 // Value of lane 0 of this lane's group.
@@ -118,15 +118,17 @@ __device__ __forceinline__ uint32_t grp_bcast0_and(uint32_t v, uint32_t mask)
     } else return grp_bcast0<G>(v) & mask;
 }
 
-// Value of lane K of this lane's group (G = 1, 2 or 4: at most one DPP quad
-// permute).
+// Value of lane K of this lane's group (G = 1, 2, 4 or 16: one DPP quad
+// permute, or for 16 lanes the row broadcast of lane K).
 template <int G, int K>
 __device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
 {
-    static_assert(G == 1 || G == 2 || G == 4, "quad permutes only");
+    static_assert(G == 1 || G == 2 || G == 4 || G == 16, "quad permutes or a row broadcast only");
+    static_assert(K >= 0 && K < G, "lane of the group");
     if constexpr (G == 1) return v;
     else if constexpr (G == 2) return dpp0<K == 0 ? DPP_QP_0022 : DPP_QP_1133>(v);
-    else return dpp0<K * 0x55>(v);                    // quad_perm [K, K, K, K]
+    else if constexpr (G == 4) return dpp0<K * 0x55>(v);    // quad_perm [K, K, K, K]
+    else return dpp0<DPP_ROW_NEWBCAST0 + K>(v);           // row_newbcast:K
 }
 
 // grp_rot_down(v) & mask with the mask folded into the row shift for 8 and

@@ -44,8 +44,12 @@ __host__ __device__ constexpr bool standard_s29(int S)
 
 // Instances whose Montgomery products inside the exponentiation take the
 // multiplier from registers (1, 2 or 4 lanes per group: at most one DPP quad
-// permute per step); the others read it from LDS.
-__host__ __device__ constexpr bool register_products(int B, int G) { return G == 1 || G == 2 || G == 4; }
+// permute per step; 16 lanes in radix 2^29: one DPP row broadcast per step);
+// the others read it from LDS.
+__host__ __device__ constexpr bool register_products(int B, int G)
+{
+    return G == 1 || G == 2 || G == 4 || (G == 16 && B < 32);
+}
 
 // Operand buffers of S * (64 / G) words in one 64-lane workgroup's LDS for a
 // sliding window of w bits: the 2^(w-1) odd powers, plus the operand buffer

@@ -51,7 +51,7 @@ struct Arith {
     {
         rmont_mul<S, G, B, true>(r, a, b, n, n0inv);
     }
-    // Lazy product with the multiplier in the group's registers (G = 2 or 4).
+    // Lazy product with the multiplier in the group's registers (G = 2, 4 or 16).
     static __device__ __forceinline__ void mont_mul_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
                                                               const uint32_t (&b)[L], const uint32_t (&n)[L],
                                                               uint32_t n0inv)
@@ -59,12 +59,12 @@ struct Arith {
         rmont_mul_regs<S, G, B, true>(r, a, b, n, n0inv);
     }
     // Lazy squares, symmetric (one product per limb pair) where kSqr: with a
-    // in registers (G = 2 or 4) or also staged in the group's slot of abuf.
+    // in registers (G = 2, 4 or 16) or also staged in the group's slot of abuf.
     static constexpr bool kSqr = rsqr_fits<B, L>();
     static __device__ __forceinline__ void sqr_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
                                                          const uint32_t (&n)[L], uint32_t n0inv)
     {
-        if constexpr (kSqr && (G == 2 || G == 4)) rmont_sqr_regs<S, G, B, true>(r, a, n, n0inv);
+        if constexpr (kSqr && (G == 2 || G == 4 || G == 16)) rmont_sqr_regs<S, G, B, true>(r, a, n, n0inv);
         else rmont_mul_regs<S, G, B, true>(r, a, a, n, n0inv);
     }
     static __device__ __forceinline__ void sqr_lds_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
