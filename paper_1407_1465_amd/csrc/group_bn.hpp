@@ -118,22 +118,17 @@ __device__ __forceinline__ uint32_t grp_bcast0_and(uint32_t v, uint32_t mask)
     } else return grp_bcast0<G>(v) & mask;
 }
 
-// Value of lane K of this lane's group (G = 1, 2, 4, 8 or 16: one DPP quad
-// permute; for 16 lanes the row broadcast of lane K; for 8 lanes the row
-// broadcast of lane K, then lanes 8-15 of the row (banks 2 and 3) take lane
-// 8 + K's by a second, bank-masked one).
+// Value of lane K of this lane's group (G = 1, 2, 4 or 16: one DPP quad
+// permute, or for 16 lanes the row broadcast of lane K).
 template <int G, int K>
 __device__ __forceinline__ uint32_t grp_bcast_lane(uint32_t v)
 {
-    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "quad permutes or row broadcasts only");
+    static_assert(G == 1 || G == 2 || G == 4 || G == 16, "quad permutes or a row broadcast only");
     static_assert(K >= 0 && K < G, "lane of the group");
     if constexpr (G == 1) return v;
     else if constexpr (G == 2) return dpp0<K == 0 ? DPP_QP_0022 : DPP_QP_1133>(v);
     else if constexpr (G == 4) return dpp0<K * 0x55>(v);    // quad_perm [K, K, K, K]
-    else if constexpr (G == 8) {
-        const uint32_t t = dpp0<DPP_ROW_NEWBCAST0 + K>(v);
-        return dpp<DPP_ROW_NEWBCAST0 + 8 + K, 0xF, 0xC>(t, v);
-    } else return dpp0<DPP_ROW_NEWBCAST0 + K>(v);         // row_newbcast:K
+    else return dpp0<DPP_ROW_NEWBCAST0 + K>(v);           // row_newbcast:K
 }
 
 // grp_rot_down(v) & mask with the mask folded into the row shift for 8 and

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys
     constexpr bool OWN = B != 32 && !standard_s29(H);     // constants not in the keyset's limb count
     __shared__ unsigned chunk;
     const int half = (int)(threadIdx.x >> 6);
-    const size_t region = (size_t)lds_entries(B, H, G, w) * Ly::WORDS;
+    const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + half * region;
     uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + region;     // wave 1's region
     const int g = grp_index<G>(), r = grp_lane<G>();

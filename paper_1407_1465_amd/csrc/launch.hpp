@@ -44,13 +44,11 @@ __host__ __device__ constexpr bool standard_s29(int S)
 
 // Instances whose Montgomery products inside the exponentiation take the
 // multiplier from registers (1, 2 or 4 lanes per group: at most one DPP quad
-// permute per step; in radix 2^29, 16 lanes: one DPP row broadcast per step,
-// and 8 lanes with at most 9 limbs per lane: two bank-masked row broadcasts
-// per step -- wider 8-lane operands would unroll past the instruction cache);
+// permute per step; 16 lanes in radix 2^29: one DPP row broadcast per step);
 // the others read it from LDS.
-__host__ __device__ constexpr bool register_products(int B, int S, int G)
+__host__ __device__ constexpr bool register_products(int B, int G)
 {
-    return G == 1 || G == 2 || G == 4 || (B < 32 && (G == 16 || (G == 8 && S <= 72)));
+    return G == 1 || G == 2 || G == 4 || (G == 16 && B < 32);
 }
 
 // Operand buffers of S * (64 / G) words in one 64-lane workgroup's LDS for a
@@ -58,16 +56,16 @@ __host__ __device__ constexpr bool register_products(int B, int S, int G)
 // the LDS-multiplier products stage A through (with register products the
 // code before and after the exponentiation borrows the table's space for
 // it); at least 4 buffers (Montgomery setup and Garner's staging use up to 3).
-__host__ __device__ constexpr int lds_entries(int B, int S, int G, int w)
+__host__ __device__ constexpr int lds_entries(int B, int G, int w)
 {
-    return ((1 << (w - 1)) + (register_products(B, S, G) ? 0 : 1)) > 4
-               ? ((1 << (w - 1)) + (register_products(B, S, G) ? 0 : 1))
+    return ((1 << (w - 1)) + (register_products(B, G) ? 0 : 1)) > 4
+               ? ((1 << (w - 1)) + (register_products(B, G) ? 0 : 1))
                : 4;
 }
 
 inline size_t lds_bytes_for(int S, int G, int B, int w)
 {
-    return (size_t)lds_entries(B, S, G, w) * (size_t)S * (size_t)(64 / G) * 4u;
+    return (size_t)lds_entries(B, G, w) * (size_t)S * (size_t)(64 / G) * 4u;
 }
 
 template <int S, int G, int B>

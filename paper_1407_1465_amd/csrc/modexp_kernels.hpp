@@ -51,7 +51,7 @@ struct Arith {
     {
         rmont_mul<S, G, B, true>(r, a, b, n, n0inv);
     }
-    // Lazy product with the multiplier in the group's registers (register_products).
+    // Lazy product with the multiplier in the group's registers (G = 2, 4 or 16).
     static __device__ __forceinline__ void mont_mul_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
                                                               const uint32_t (&b)[L], const uint32_t (&n)[L],
                                                               uint32_t n0inv)
@@ -59,12 +59,12 @@ struct Arith {
         rmont_mul_regs<S, G, B, true>(r, a, b, n, n0inv);
     }
     // Lazy squares, symmetric (one product per limb pair) where kSqr: with a
-    // in registers (register_products, G > 1) or also staged in the group's slot of abuf.
+    // in registers (G = 2, 4 or 16) or also staged in the group's slot of abuf.
     static constexpr bool kSqr = rsqr_fits<B, L>();
     static __device__ __forceinline__ void sqr_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
                                                          const uint32_t (&n)[L], uint32_t n0inv)
     {
-        if constexpr (kSqr && G > 1 && register_products(B, S, G)) rmont_sqr_regs<S, G, B, true>(r, a, n, n0inv);
+        if constexpr (kSqr && (G == 2 || G == 4 || G == 16)) rmont_sqr_regs<S, G, B, true>(r, a, n, n0inv);
         else rmont_mul_regs<S, G, B, true>(r, a, a, n, n0inv);
     }
     static __device__ __forceinline__ void sqr_lds_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
@@ -307,7 +307,7 @@ struct ExpBits {
 // schedule; the wave executes one Montgomery product per slot for all its
 // groups, a squaring or a table product per group (the multiplier is
 // selected per group), until every group is done, so the loop holds a single
-// copy of the product.  With register_products(B, S, G) the multiplier comes
+// copy of the product.  With register_products(B, G) the multiplier comes
 // from registers (DPP broadcast; the table starts at the LDS base); otherwise
 // A is staged through the operand buffer at the LDS base (the table follows
 // it) and each group's product reads its own multiplier there or in its
@@ -328,7 +328,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
     using Ly = Layout<S, G>;
     using Ar = Arith<S, G, B>;
     constexpr int L = Ly::L;
-    constexpr bool REG = register_products(B, S, G);
+    constexpr bool REG = register_products(B, G);
     uint32_t *abuf = lds;                       // operand buffer (LDS-multiplier products)
     uint32_t *tbl = REG ? lds : lds + Ly::WORDS;   // entry k at tbl + k * WORDS
     const int g = grp_index<G>();
@@ -582,7 +582,7 @@ __global__ __launch_bounds__(128) void k_crt(const uint32_t *__restrict__ c, con
     using Ly = Layout<H, G>;
     constexpr int L = H / G, NG = 64 / G;
     const int half = (int)(threadIdx.x >> 6);
-    const size_t region = (size_t)lds_entries(B, H, G, w) * Ly::WORDS;
+    const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + half * region;
     uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + region;     // wave 1's region
     const int g = grp_index<G>(), r = grp_lane<G>();

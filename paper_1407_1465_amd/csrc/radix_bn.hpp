@@ -337,7 +337,7 @@ struct RRegBlocks {
 };
 
 // r = a * b * 2^(-B*S) mod n with both operands in the group's registers and
-// the multiplier limbs broadcast by DPP (no LDS round trip); G = 2, 4, 8 or 16.
+// the multiplier limbs broadcast by DPP (no LDS round trip); G = 2, 4 or 16.
 // Same bounds and LAZY meaning as rmont_mul; r may alias a or b.
 template <int S, int G, int B, bool LAZY>
 __device__ __forceinline__ void rmont_mul_regs(uint32_t (&r)[S / G], const uint32_t (&a)[S / G],
@@ -409,7 +409,7 @@ struct RSqrBlocks {
     }
 };
 
-// r = a * a * 2^(-B*S) mod n with a in the group's registers (G = 2, 4, 8 or 16):
+// r = a * a * 2^(-B*S) mod n with a in the group's registers (G = 2, 4 or 16):
 // S * (L + 1) / 2 products per lane for the square instead of S * L.  Same
 // bounds and LAZY meaning as rmont_mul; r may alias a.
 template <int S, int G, int B, bool LAZY>
