@@ -58,8 +58,8 @@ __device__ __forceinline__ constexpr uint64_t top_lanes_mask()
 //
 // Groups of up to 16 lanes never straddle a DPP row, so the moves below are
 // DPP data movements (no LDS round trip): quad_perm for groups of 2 and 4,
-// row shifts with bank masks for 8 and 16, and for the broadcast of a 16-lane
-// group's lane 0 the row broadcast that CDNA3/4 DPP provides.
+// row shifts with bank masks for 8 and 16, and for the broadcast of any lane
+// of a 16-lane group the row broadcast that CDNA3/4 DPP provides.
 
 template <int CTRL, int ROW_MASK = 0xF, int BANK_MASK = 0xF>
 __device__ __forceinline__ uint32_t dpp(uint32_t old, uint32_t v)
