@@ -493,8 +493,12 @@ def main():
                 diff = back.cpu().numpy().view(np.uint32) != ins
                 bad += int(np.logical_or.reduceat(diff, offs[:-1]).sum())
             return bad, len(items)
-        # saturated rate: a closed burst
-        sat = run(poisson_requests(0.0, 400, W.SEED_BASE + 50, limbs, mods))
+        # saturated rate: the median of three closed bursts, after one
+        # unmeasured burst (first launches of every plan)
+        run(poisson_requests(0.0, 400, W.SEED_BASE + 49, limbs, mods))
+        bursts = sorted((run(poisson_requests(0.0, 400, W.SEED_BASE + 50 + 10 * i, limbs, mods))
+                         for i in range(3)), key=lambda b: b["requests_per_s"])
+        sat = bursts[1]
         rate = 0.7 * sat["requests_per_s"]
         nreq = max(200, int(rate * args.serve_seconds))
         st = run(poisson_requests(rate, nreq, W.SEED_BASE + 51, limbs, mods))
@@ -508,7 +512,9 @@ def main():
         line.update(metric="RSA serving (2048/4096-bit keys, 70% CRT decrypt): requests/s at p50/p99 latency",
                     unit="requests/s",
                     config={"workload": "rsa-serve-2048-4096", "keys": len(keys), "rate_req_per_s": rate,
-                            "saturated_req_per_s": sat["requests_per_s"], "requests": st["requests"]})
+                            "saturated_req_per_s": sat["requests_per_s"],
+                            "saturation_bursts_req_per_s": [b["requests_per_s"] for b in bursts],
+                            "requests": st["requests"]})
         line["latency_ms"] = {"p50": st["p50_ms"], "p99": st["p99_ms"], "mean": st["mean_ms"]}
         line["ops_per_s"] = st["ops_per_s"]
         value = st["requests_per_s"]
