@@ -18,11 +18,13 @@
  *     asynchronous: the call returns before the results exist.  No entry
  *     point synchronises the device except rsa_device_errors.
  *   - Operands and the window table of each exponentiation live in
- *     registers and LDS.  rsa_modexp_batch and rsa_ops_batch allocate no
- *     device memory per call; rsa_decrypt_crt_batch takes its key-ordering
- *     scratch from the device's memory pool, stream-ordered (see there);
- *     rsa_autotune and rsa_keyset_create allocate their own buffers.  The
- *     per-device state is an 8-byte error counter made once (rsa_init).
+ *     registers and LDS.  No entry point allocates device memory per call:
+ *     rsa_modexp_batch needs no scratch, rsa_ops_batch takes a caller
+ *     workspace, and rsa_decrypt_crt_batch keeps one key-ordering buffer per
+ *     device and stream handle, made the first time that stream needs one
+ *     of its size (see there).  rsa_autotune and rsa_keyset_create allocate
+ *     their own buffers.  The per-device error counter is static device
+ *     memory.
  *   - Host-checkable errors are returned before any HIP call.  Per-element
  *     data errors (an even or unit modulus, p <= q for CRT) write 0 to that
  *     element's output and increment a per-device counter that
@@ -89,10 +91,17 @@ int rsa_modexp_batch(const uint32_t *base, const uint32_t *exp, const uint32_t *
  * c must be < p*q (it is the caller's ciphertext).
  * Messages under the same key are processed together (one exponent per
  * wave): for more than one workgroup's worth of messages the call orders
- * them by a hash of their key words in scratch taken from the device's
- * default memory pool with stream-ordered allocation on `stream` (4 bytes
- * per message + 256 KiB, released on the same stream); if that allocation
- * fails it runs in the given order.  The order never changes a result.
+ * them by a hash of their key words, in a scratch buffer (4 bytes per
+ * message + 256 KiB) that the library keeps for the current device and this
+ * stream handle.  The first call on a stream, and a call with a larger
+ * batch than that stream has seen, allocates it (hipMalloc; an outgrown
+ * buffer is kept until the process ends, so graphs captured earlier stay
+ * valid); later calls allocate nothing.  While `stream` is being captured
+ * into a graph the call never allocates: without a large enough buffer the
+ * batch runs in the given order (warm a stream up before capturing on it).
+ * If an allocation fails the batch also runs in the given order.  The order
+ * never changes a result.  Calls on distinct streams use distinct buffers;
+ * calls on one stream are ordered by the stream.
  */
 int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *q,
                           const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,
@@ -150,10 +159,9 @@ int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int wind
 int rsa_autotune(int limbs, int kind, int exp_bits, size_t count, hipStream_t stream, rsa_plan *best);
 
 /*
- * Sets up the current device's library state (the data-error counter, one
- * 8-byte device allocation made once per device).  Every other entry point
- * does this on first use; call it explicitly before capturing any library
- * call into a HIP graph.
+ * Sets up the current device's library state (looks up the address of the
+ * data-error counter, static device memory; allocates nothing).  Every
+ * other entry point does this on first use.
  */
 int rsa_init(void);
 
@@ -213,7 +221,9 @@ int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, const uint32_t
 
 /*
  * Number of per-element data errors counted on the current device since the
- * last call, then reset to zero.  Synchronises `stream` first.
+ * last call, reset to zero in the same atomic step (a one-thread kernel on
+ * `stream`), so counts added later, by work on any stream, go to the next
+ * call.  Synchronises `stream` (only) and returns the count.
  */
 int rsa_device_errors(hipStream_t stream, uint64_t *n_bad);
 

@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 namespace rsagpu {
 
 static const int kBucketBits = 16;
@@ -84,32 +87,9 @@ __global__ void k_order_place(const uint32_t *p, const uint32_t *dp, const uint3
     order[at] = (unsigned)i;
 }
 
-// Stream-ordered scratch from the device's default pool, kept cached by the
-// pool between calls.
-static void keep_pool_memory()
+static hipError_t launch_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
+                               unsigned *cnt, unsigned *order, hipStream_t stream)
 {
-    static bool done[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t keep = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
-    done[dev] = true;
-}
-
-unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
-                    hipStream_t stream)
-{
-    if (count > 0xFFFFFFFFull) return nullptr;
-    keep_pool_memory();
-    void *mem = nullptr;
-    if (hipMallocAsync(&mem, (count + kBuckets) * sizeof(unsigned), stream) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-    }
-    unsigned *cnt = static_cast<unsigned *>(mem), *order = cnt + kBuckets;
     const unsigned blocks = (unsigned)((count + 255) / 256);
     hipLaunchKernelGGL(k_order_clear, dim3(kBuckets / 256), dim3(256), 0, stream, cnt);
     hipLaunchKernelGGL(k_order_count, dim3(blocks), dim3(256), 0, stream, p, dp, dq, (unsigned long long)count, hl,
@@ -117,16 +97,70 @@ unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, s
     hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, stream, cnt);
     hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(256), 0, stream, p, dp, dq, (unsigned long long)count, hl,
                        cnt, order);
-    if (hipGetLastError() != hipSuccess) {
-        (void)hipFreeAsync(mem, stream);
-        return nullptr;
-    }
-    return order;
+    return hipGetLastError();
 }
 
-void free_key_order(unsigned *order, hipStream_t stream)
+// Scratch of the plain CRT call: one buffer per (device, stream handle),
+// made on the first call that needs it and grown (doubling) when a larger
+// batch arrives; a call therefore allocates only the first time a stream
+// sees a batch of its size.  Buffers are never released while the process
+// runs: an outgrown buffer is kept, since a HIP graph captured earlier may
+// still name it.  Calls on one stream reuse its buffer in stream order;
+// calls on distinct streams use distinct buffers.
+namespace {
+struct StreamScratch {
+    int dev;
+    hipStream_t stream;
+    void *mem;
+    size_t bytes;
+};
+std::mutex g_scratch_mu;
+std::vector<StreamScratch> g_scratch;
+std::vector<void *> g_outgrown;
+}  // namespace
+
+size_t key_order_bytes(size_t count) { return (count + kBuckets) * sizeof(unsigned); }
+
+unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
+                    hipStream_t stream)
 {
-    if (order) (void)hipFreeAsync(order - kBuckets, stream);
+    if (count > 0xFFFFFFFFull) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    const size_t need = key_order_bytes(count);
+    void *mem = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        StreamScratch *s = nullptr;
+        for (StreamScratch &x : g_scratch)
+            if (x.dev == dev && x.stream == stream) s = &x;
+        if (s && s->bytes >= need) {
+            mem = s->mem;
+        } else {
+            // no allocation while the stream is being captured into a graph:
+            // the batch then runs in the given order
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            const size_t bytes = s && 2 * s->bytes > need ? 2 * s->bytes : need;
+            if (hipMalloc(&mem, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            if (s) {
+                g_outgrown.push_back(s->mem);
+                s->mem = mem;
+                s->bytes = bytes;
+            } else {
+                g_scratch.push_back(StreamScratch{dev, stream, mem, bytes});
+            }
+        }
+    }
+    unsigned *cnt = static_cast<unsigned *>(mem), *order = cnt + kBuckets;
+    if (launch_order(p, dp, dq, count, hl, cnt, order, stream) != hipSuccess) return nullptr;
+    return order;
 }
 
 }  // namespace rsagpu

@@ -39,14 +39,16 @@ bool resolve(int limbs, int kind, Resolved *r);
 static const size_t kBulkOps = 16384;
 
 // Processing order of a plain CRT batch that puts messages under the same key
-// next to each other (device array of count indices in stream-ordered
-// scratch), or nullptr to keep the given order; free_key_order releases it
-// after the work that reads it has been queued on the same stream.
+// next to each other (device array of count indices), or nullptr to keep the
+// given order.  The scratch (key_order_bytes(count)) is the library's buffer
+// for this device and stream handle, made or grown on first need (never while
+// the stream is being captured: the given order is kept then).
+size_t key_order_bytes(size_t count);
 unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
                     hipStream_t stream);
-void free_key_order(unsigned *order, hipStream_t stream);
 
-// Per-device data-error counter (allocated once per device).
+// Per-device data-error counter: two words of static device memory (the
+// count, and the value rsa_device_errors last took), looked up once per device.
 int device_state(unsigned long long **errs);
 int status_of(hipError_t e);
 

@@ -130,6 +130,13 @@ bool resolve(int limbs, int kind, Resolved *r)
 }
 
 // ---- per-device state: the data-error counter ------------------------------
+//
+// Word 0 counts per-element data errors (kernels add to it atomically); word
+// 1 receives the count rsa_device_errors takes.  Static device memory: each
+// device holds its own copy, zero when the code object loads, at an address
+// looked up once per device.
+
+static __device__ __align__(256) unsigned long long g_err_words[2];
 
 static const int kMaxDevices = 64;
 static unsigned long long *g_errs[kMaxDevices];
@@ -142,17 +149,15 @@ int device_state(unsigned long long **errs)
     std::lock_guard<std::mutex> lock(g_dev_mutex);
     if (!g_errs[dev]) {
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, sizeof(unsigned long long));
-        if (e != hipSuccess) return e == hipErrorOutOfMemory ? RSA_ENOMEM : RSA_EHIP;
-        e = hipMemset(p, 0, sizeof(unsigned long long));
-        if (e != hipSuccess) return RSA_EHIP;
-        e = hipDeviceSynchronize();
-        if (e != hipSuccess) return RSA_EHIP;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_words)) != hipSuccess || !p) return RSA_EHIP;
         g_errs[dev] = static_cast<unsigned long long *>(p);
     }
     *errs = g_errs[dev];
     return RSA_OK;
 }
+
+// Moves the error count into word 1 and clears it, in one atomic step.
+__global__ void k_take_errors(unsigned long long *w) { w[1] = atomicExch(&w[0], 0ull); }
 
 int status_of(hipError_t e)
 {
@@ -201,10 +206,8 @@ extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const
     const int st = device_state(&errs);
     if (st != RSA_OK) return st;
     // more than one workgroup: process the messages grouped by key
-    unsigned *order = count > ng ? key_order(p, dp, dq, count, limbs / 2, stream) : nullptr;
-    const int rc = status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, count, limbs / 2, r.w, errs, stream));
-    free_key_order(order, stream);
-    return rc;
+    const unsigned *order = count > ng ? key_order(p, dp, dq, count, limbs / 2, stream) : nullptr;
+    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, count, limbs / 2, r.w, errs, stream));
 }
 
 extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)
@@ -247,14 +250,14 @@ extern "C" int rsa_device_errors(hipStream_t stream, uint64_t *n_bad)
     unsigned long long *errs = nullptr;
     int st = device_state(&errs);
     if (st != RSA_OK) return st;
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return status_of(e);
+    // one caller at a time per process: word 1 is shared
+    static std::mutex take_mu;
+    std::lock_guard<std::mutex> lock(take_mu);
+    hipLaunchKernelGGL(k_take_errors, dim3(1), dim3(1), 0, stream, errs);
+    hipError_t e = hipGetLastError();
     unsigned long long v = 0;
-    e = hipMemcpy(&v, errs, sizeof(v), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return status_of(e);
-    e = hipMemset(errs, 0, sizeof(v));
-    if (e != hipSuccess) return status_of(e);
-    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpyAsync(&v, errs + 1, sizeof(v), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return status_of(e);
     *n_bad = v;
     return RSA_OK;

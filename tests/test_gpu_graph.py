@@ -1,5 +1,6 @@
 """The entry points captured in a HIP graph (torch.cuda.graph) and replayed:
-plain CRT decryption (with its key ordering and pooled scratch), plain
+plain CRT decryption (with its key ordering in the stream's library buffer,
+or in the given order on a stream captured before it ever ran the call), plain
 exponentiation and a keyset batch (with its bucket sort and forked bucket
 streams).  Each of several replays, with eager work and synchronisation
 between them, must equal the eager results."""
@@ -49,6 +50,10 @@ def test_graph_capture_and_replay():
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
+        # warm-up on the capture stream: the CRT call's key-order buffer for
+        # this stream exists before capture (a capture never allocates)
+        rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out_crt)
+        s.synchronize()
         with torch.cuda.graph(g, stream=s):
             rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out_crt)
             rsagpu.modexp(out_crt, e, n, out=out_enc)
@@ -67,4 +72,22 @@ def test_graph_capture_and_replay():
         assert torch.equal(eager, ref_crt)
     assert rsagpu.device_errors() == 0
     del g
+
+    # a stream that never ran the CRT call: the captured call allocates
+    # nothing and keeps the given order; the results are the same
+    g2 = torch.cuda.CUDAGraph()
+    s2 = torch.cuda.Stream()
+    s2.wait_stream(torch.cuda.current_stream())
+    out2 = torch.zeros_like(c)
+    with torch.cuda.stream(s2):
+        with torch.cuda.graph(g2, stream=s2):
+            rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out2)
+    torch.cuda.current_stream().wait_stream(s2)
+    for _ in range(2):
+        out2.zero_()
+        g2.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out2, ref_crt)
+    del g2
+    assert rsagpu.device_errors() == 0
     ks.close()
