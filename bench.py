@@ -8,18 +8,25 @@ decryption pass over the whole batch with inputs resident in HBM.  The JSON
 line carries
 
   roofline:     the decryption kernel against the chip's 32x32-bit integer
-                multiply peak: algorithmic products per launch (Montgomery
-                products of the sliding-window schedule the plan runs,
-                counted from the actual exponents, 2h^2 + h per product and
-                h(h+1)/2 + h^2 + h per squaring where the kernel squares
-                with one product per limb pair, plus the recombination)
-                over the kernel's mean launch time from HIP events recorded
-                on the stream it runs on (frac_squarings_as_products: the
-                same with every squaring counted at 2h^2 + h);
-  cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) timed on a bounded
-                sample of the same messages on the host's cores;
-  latency_ms:   p50 and p99 of the per-step (whole-batch) time over the
-                timed steps;
+                multiply peak (256 CUs x 64 lanes x 2.4 GHz, one
+                v_mad_u64_u32 per lane per clock).  `achieved` counts the
+                method's algorithmic products per unit - the k-ary method of
+                Section 3.6.4 at the window that minimises them, every
+                squaring a general Montgomery product of 2s^2 + s 32x32-bit
+                products, conversions included, and for CRT the two
+                reductions of c and Garner's recombination - times the units
+                of one launch, over the mean step time from HIP events on the
+                launch stream.  `as_run` gives the tighter count of the
+                schedule the kernel runs (sliding window, symmetric
+                squarings), `peak_measured` the multiply rate the probe
+                library sustains in the same run;
+  cpu_baseline: the plain CPU oracle (C^d mod n, no CRT) on the host's
+                cores, over the whole batch (every GPU output compared), and
+                on one thread over a fixed 256-message prefix;
+  latency_ms:   p50 and p99 request latency of a short serving run
+                (Poisson arrivals at 0.7 x the saturated rate, 2048/4096-bit
+                keys, 70% CRT decryptions); batch_ms: p50/p99 of the whole-
+                batch step time;
   check:        elements of the whole batch whose round trip through the
                 opposite operation (decryptions re-encrypted, encryptions
                 decrypted) differs; the run fails unless it is 0.
@@ -31,7 +38,8 @@ through the continuous-batching server: p50/p99 latency and throughput),
 paper (the paper's own Section 10 experiment: one-word keys n = 131*137 and
 1009*509, e = 131, messages 0..800 at every data size of Tables 1 and 2,
 beside the times the tables print, whose unit the paper leaves unclear),
-keygen (4096-bit key generation with the Miller-Rabin rounds on the GPU).
+keygen (4096-bit key generation with the Miller-Rabin rounds on the GPU),
+mulpeak (the issue rate of the 32-bit integer multiplies, libmulpeak.so).
 """
 import argparse
 import json
@@ -130,6 +138,79 @@ def modexp_products(key, e: int, plan) -> int:
     return exp_products(e, plan, key.limbs)
 
 
+# ---- the method's algorithmic products per unit (k-ary count) --------------
+
+def kary_montmuls(bits: int):
+    """(T, w): Montgomery products of one exponentiation with a `bits`-bit
+    exponent by the k-ary method (Section 3.6.4, Fig. 6) at the window w that
+    minimises T = (ceil(bits/w) - 1)(w + 1) + 2^w: w squarings and one table
+    product per further digit, and 2^w for the table of powers x^0 .. x^(2^w-1)
+    with the conversions into and out of Montgomery form."""
+    return min(((-(-bits // w) - 1) * (w + 1) + (1 << w), w) for w in range(1, 12))
+
+
+def unit_exp_products(s: int, bits: int = 0) -> int:
+    """32x32-bit products of x^d mod n, n and d of s 32-bit limbs (full-length
+    d unless `bits` is given), every squaring a general product."""
+    return kary_montmuls(bits or 32 * s)[0] * mont_products(s)
+
+
+def unit_enc_products(s: int) -> int:
+    """The same for e = 65537 by the binary method of Fig. 5: 16 squarings,
+    one product and the two conversions."""
+    return 19 * mont_products(s)
+
+
+def unit_crt_products(h: int) -> int:
+    """One CRT decryption of a 2h-limb modulus: per half the reduction of c
+    (h^2 + h) and a full-length h-limb exponentiation, then Garner's
+    recombination (a Montgomery product and the h x h product h*q)."""
+    return 2 * (unit_exp_products(h) + h * h + h) + mont_products(h) + h * h
+
+
+# ---- host and probe ----------------------------------------------------------
+
+def host_cpus():
+    """(cpus this process may run on, logical CPUs of the host, CPU model):
+    the first is the affinity set, lowered to the cgroup quota if one is set."""
+    n = os.cpu_count() or 1
+    share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else n
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            quota, period = f.read().split()[:2]
+        if quota != "max":
+            share = max(1, min(share, -(-int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return share, n, model
+
+
+def oracle_threads():
+    """Threads for the CPU oracle: the CPUs this process may use, at most 16
+    (the CPU share that goes with one GPU on the machines this runs on)."""
+    return min(16, host_cpus()[0])
+
+
+def measured_peak(quick: bool = True):
+    """v_mad_u64_u32 issue rate from the probe library (products/s), or None."""
+    try:
+        from paper_1407_1465_amd import mulpeak
+        r = mulpeak.measure(0, iters=4096 if quick else 8192, reps=3 if quick else 7)
+    except (ImportError, RuntimeError, OSError) as e:
+        print("# multiply probe unavailable: %s" % e, file=sys.stderr, flush=True)
+        return None
+    return r
+
+
 def timed(fn, steps, warmup, torch, per_step=None):
     """Mean ms per step over `steps` back-to-back steps (HIP events on the
     launch stream); per_step, if a list, receives each step's ms."""
@@ -192,24 +273,148 @@ def measured_traffic(kernel):
     return t.get("traffic_bytes_per_launch")
 
 
-def roofline(products, ms, kernel):
+def roofline(products, ms, kernel, per_unit=None, units=None, as_run=None, peak=None):
+    """Roofline object of the dominant kernel: `products` algorithmic 32x32-bit
+    products per launch (per_unit x units) over `ms` per launch; `as_run` the
+    products of the schedule the kernel runs (for its fraction beside);
+    `peak` the probe's measured multiply rate."""
     achieved = products / (ms / 1e3)
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_MUL_PEAK / 1e12,
-            "unit": "T int32-mul/s", "frac": achieved / INT32_MUL_PEAK, "traffic": measured_traffic(kernel),
-            "kernel": kernel, "products_per_launch": products}
+    r = {"bound": "alu", "achieved": achieved / 1e12, "peak": INT32_MUL_PEAK / 1e12,
+         "unit": "T int32-mul/s", "frac": achieved / INT32_MUL_PEAK, "traffic": measured_traffic(kernel),
+         "kernel": kernel, "products_per_launch": products, "products_per_unit": per_unit,
+         "units_per_launch": units, "ms_per_launch": ms}
+    if as_run is not None:
+        r["as_run"] = {"products_per_launch": as_run, "frac": as_run / (ms / 1e3) / INT32_MUL_PEAK,
+                       "count": "sliding window as run, squarings at the symmetric cost where the kernel "
+                                "squares with one product per limb pair"}
+    if peak is not None:
+        r["peak_measured"] = {"value": peak["ops_per_s"] / 1e12, "unit": "T int32-mul/s", "op": peak["op"],
+                              "frac_of_nominal": peak["ops_per_s"] / INT32_MUL_PEAK}
+        r["frac_of_measured_peak"] = achieved / peak["ops_per_s"]
+    return r
 
 
-def cpu_baseline(oracle, base, exp, mod, gpu_out, ns, unit, what):
-    threads = min(16, os.cpu_count() or 1)
-    c0 = time.process_time()
-    got, cwall, used = oracle.modexp_batch(base[:ns], exp[:ns], mod[:ns], nthreads=threads)
-    ccpu = time.process_time() - c0
+def cpu_baseline(oracle, base, exp, mod, gpu_out, unit, what, count=None, prefix=256):
+    """The oracle on the host's cores over the first `count` elements (all by
+    default), every output compared with the GPU's, and on one thread over the
+    first `prefix` elements."""
     import numpy as np
-    if not np.array_equal(got, gpu_out[:ns]):
-        raise SystemExit("GPU output differs from the oracle on the CPU sample")
-    return {"value": ns / cwall, "unit": unit, "cores": used, "kind": "oracle",
-            "sample": "first %d messages of the same batch, %s, %.1f s wall, %.1f s CPU"
-                      % (ns, what, cwall, ccpu)}
+    share, ncpu, model = host_cpus()
+    threads = oracle_threads()
+    n = len(base) if count is None else min(count, len(base))
+    k = min(prefix, n)
+    one, wall1, _ = oracle.modexp_batch(base[:k], exp[:k], mod[:k], nthreads=1)
+    c0 = time.process_time()
+    got, cwall, used = oracle.modexp_batch(base[:n], exp[:n], mod[:n], nthreads=threads)
+    ccpu = time.process_time() - c0
+    bad = int((got != gpu_out[:n]).any(axis=1).sum())
+    if bad or not np.array_equal(one, got[:k]):
+        raise SystemExit("GPU output differs from the oracle on %d of %d elements" % (bad, n))
+    return {"value": n / cwall, "unit": unit, "cores": used, "kind": "oracle",
+            "sample": "%s %d elements of the same batch, %s, %.1f s wall, %.1f s CPU; every output equals "
+                      "the GPU's" % ("all" if n == len(base) else "the first", n, what, cwall, ccpu),
+            "verified": n, "mismatches": bad, "cpu_model": model, "host_cpus": ncpu, "cpu_share": share,
+            "one_thread": {"value": k / wall1, "unit": unit, "sample": "first %d elements" % k}}
+
+
+def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0):
+    """Serving run (256 x 2048-bit + 64 x 4096-bit resident keys, 70% CRT
+    decryptions, 1..256 messages per request): the saturated request rate as
+    the median of three closed bursts of 400 requests (after one unmeasured
+    burst), then Poisson arrivals at 0.7 x that rate for `seconds`; every
+    served message checked through the opposite operation afterwards.  With
+    plain_requests > 0 also the rate of the plain form: the same kind of
+    requests, one launch of the plain entry points per request (device-
+    resident inputs, no host copies), back to back on one stream."""
+    from paper_1407_1465_amd.serve import GpuExecutor, Server, poisson_requests
+    keys = W.make_keys(2048, W.SEED_BASE + 5, 256) + W.make_keys(4096, W.SEED_BASE + 5, 64)
+    ks = rsagpu.KeySet(len(keys))
+    for k in keys:
+        ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
+    limbs = [k.limbs for k in keys]
+    mods = [k.n for k in keys]
+    pool, max_ops = 1 << 23, 1 << 16
+    ex = GpuExecutor(ks, limbs, pool, max_ops)
+    last = {}
+
+    def run(reqs):
+        srv = Server(ex, pool, max_inflight=ex.max_inflight, max_ops=max_ops)
+        srv.run(reqs)
+        last["finished"] = srv.finished
+        return srv.stats()
+
+    def verify(finished):
+        items = [(r.kind, r.key_id, row) for r in finished if r.error is None
+                 for row in zip(r.outputs, r.inputs)]
+        bad, chunk = 0, 1 << 15
+        ws_v = torch.empty(rsagpu.ops_workspace_size(chunk), dtype=torch.uint8, device="cuda")
+        for i0 in range(0, len(items), chunk):
+            part = items[i0:i0 + chunk]
+            offs = np.cumsum([0] + [limbs[kid] for _, kid, _ in part])
+            outs = np.concatenate([o for _, _, (o, _) in part]).astype(np.uint32)
+            ins = np.concatenate([x for _, _, (_, x) in part]).astype(np.uint32)
+            vops = rsagpu.pack_ops(np.array([1 - k for k, _, _ in part]), np.array([kid for _, kid, _ in part]),
+                                   offs[:-1], offs[:-1]).cuda()
+            back = torch.zeros(int(offs[-1]), dtype=torch.int32, device="cuda")
+            rsagpu.ops_batch(ks, vops, _dev(torch, np, outs), back, ws_v)
+            diff = back.cpu().numpy().view(np.uint32) != ins
+            bad += int(np.logical_or.reduceat(diff, offs[:-1]).sum())
+        return bad, len(items)
+
+    def req_products(r):
+        k = keys[r.key_id]
+        return len(r.inputs) * (unit_crt_products(k.limbs // 2) if r.kind else unit_enc_products(k.limbs))
+
+    run(poisson_requests(0.0, 400, W.SEED_BASE + 49, limbs, mods))
+    bursts = sorted((run(poisson_requests(0.0, 400, W.SEED_BASE + 50 + 10 * i, limbs, mods))
+                     for i in range(3)), key=lambda b: b["requests_per_s"])
+    sat = bursts[1]
+    rate = 0.7 * sat["requests_per_s"]
+    nreq = max(200, int(rate * seconds))
+    st = run(poisson_requests(rate, nreq, W.SEED_BASE + 51, limbs, mods))
+    finished = last["finished"]
+    bad, nmsg = verify(finished)
+    errs = rsagpu.device_errors()
+    products = sum(req_products(r) for r in finished if r.error is None)
+    out = {"requests_per_s": st["requests_per_s"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+           "mean_ms": st["mean_ms"], "ops_per_s": st["ops_per_s"], "requests": st["requests"],
+           "rate_req_per_s": rate, "saturated_req_per_s": sat["requests_per_s"],
+           "saturation_bursts_req_per_s": [b["requests_per_s"] for b in bursts], "span_s": st["span_s"],
+           "streams": len(ex.streams), "max_inflight": ex.max_inflight,
+           "check": {"mismatches": bad + st["errors"] + errs,
+                     "of": "all %d served messages through the opposite operation, plus failed requests "
+                           "and device data errors" % nmsg},
+           "products": products}
+    if plain_requests:
+        reqs = poisson_requests(0.0, plain_requests, W.SEED_BASE + 52, limbs, mods)
+        launches = []
+        for r in reqs:
+            k = keys[r.key_id]
+            L, h, cnt = k.limbs, k.limbs // 2, len(r.inputs)
+            x = _dev(torch, np, r.inputs)
+            if r.kind:
+                args = [_dev(torch, np, np.tile(W.int_to_limbs(getattr(k, a), h), (cnt, 1)))
+                        for a in ("p", "q", "dp", "dq", "qinv")]
+                launches.append(("crt", x, args, torch.empty_like(x)))
+            else:
+                args = [_dev(torch, np, np.tile(W.int_to_limbs(getattr(k, a), L), (cnt, 1))) for a in ("e", "n")]
+                launches.append(("enc", x, args, torch.empty_like(x)))
+
+        def plain():
+            for kind, x, args, o in launches:
+                if kind == "crt":
+                    rsagpu.decrypt_crt(x, *args, out=o)
+                else:
+                    rsagpu.modexp(x, *args, out=o)
+        ms_plain, _ = timed(plain, 2, 1, torch)
+        out["plain_one_request_per_launch"] = {"requests_per_s": len(reqs) / (ms_plain / 1e3),
+                                               "requests": len(reqs), "ms": ms_plain}
+    ks.close()
+    return out
+
+
+def _dev(torch, np, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
 
 
 def main():
@@ -218,11 +423,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="crt2048",
-                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve", "paper", "keygen"])
+                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve", "paper", "keygen",
+                             "mulpeak"])
     ap.add_argument("--count", type=int, default=0, help="messages (0: the workload's size)")
-    ap.add_argument("--cpu-sample", type=int, default=1536,
-                    help="messages the CPU oracle processes for the baseline (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--cpu-sample", type=int, default=-1,
+                    help="elements the CPU oracle processes for the baseline (-1: the whole batch, 0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=None,
+                    help="length of the Poisson serving run (serve: 8 s; the default workload adds a 3 s run "
+                         "for its request latencies, 0 leaves it out)")
+    ap.add_argument("--no-tune", action="store_true", help="mixed: keep the default plans (no autotuning)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference "
                          "dispatch for hardware traffic counters)")
@@ -253,6 +462,8 @@ def main():
     def tab(wl, attr, width):
         return np.ascontiguousarray(W.ints_to_limbs([getattr(k, attr) for k in wl.keys], width)[wl.key_of])
 
+    if args.serve_seconds is None:
+        args.serve_seconds = 8.0 if args.workload == "serve" else 3.0
     line = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "u32",
             "data": "synthetic (seeded keys and messages)"}
@@ -273,9 +484,8 @@ def main():
             steps_ms = []
             ms, wall = timed(lambda: rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out), args.steps, args.warmup,
                              torch, steps_ms)
-            # latency of one whole batch (steps back to back on the stream)
-            line["latency_ms"] = {"p50": percentile(steps_ms, 50), "p99": percentile(steps_ms, 99),
-                                  "of": "one batch of %d decryptions" % count}
+            line["batch_ms"] = {"p50": percentile(steps_ms, 50), "p99": percentile(steps_ms, 99),
+                                "of": "one batch of %d decryptions" % count}
             # every decryption re-encrypted (e = 65537) must give its ciphertext back
             back = rsagpu.modexp(out, dev(e_h), dev(n_h))
             bad = row_mismatches(back, c)
@@ -283,7 +493,7 @@ def main():
                                                       "ciphertexts" % count}
             if bad:
                 raise SystemExit("round-trip check failed on %d elements" % bad)
-            products = per_key_sum(wl.key_of, lambda k: crt_products(wl.keys[k], plan))
+            as_run = per_key_sum(wl.key_of, lambda k: crt_products(wl.keys[k], plan))
             # the same batch as one launch per key (plain form, no cross-key batching)
             per_key = []
             for j in range(len(wl.keys)):
@@ -301,16 +511,26 @@ def main():
                         config={"workload": "rsa2048-crt-decrypt", "keys": len(wl.keys), "messages": count,
                                 "modulus_bits": 32 * L, "radix_bits": plan.radix_bits,
                                 "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
-            line["roofline"] = roofline(products, ms, "k_crt<%d,%d,%d>" % (plan.padded_limbs, plan.lanes_per_op,
-                                                                           plan.radix_bits))
-            # the same fraction with every squaring counted as a general product
-            general = per_key_sum(wl.key_of, lambda k: crt_products(wl.keys[k], plan, True))
-            line["roofline"]["frac_squarings_as_products"] = general / (ms / 1e3) / INT32_MUL_PEAK
+            per_unit = unit_crt_products(h)
+            line["roofline"] = roofline(per_unit * count, ms, "k_crt<%d,%d,%d>" % (plan.padded_limbs,
+                                                                                   plan.lanes_per_op,
+                                                                                   plan.radix_bits),
+                                        per_unit, count, as_run, measured_peak())
             if args.cpu_sample:
                 import oracle
-                cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32),
-                                   min(args.cpu_sample, count), "decryptions/s",
-                                   "plain C^d mod n (no CRT)")
+                cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32), "decryptions/s",
+                                   "plain C^d mod n (no CRT)",
+                                   None if args.cpu_sample < 0 else min(args.cpu_sample, count))
+            if args.serve_seconds > 0:
+                sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds)
+                if sv["check"]["mismatches"]:
+                    raise SystemExit("serving run reported errors")
+                line["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"],
+                                      "of": "served requests: Poisson arrivals at 0.7 x the saturated rate, "
+                                            "256 x 2048-bit + 64 x 4096-bit keys, 70% CRT decryptions, "
+                                            "1-256 messages each"}
+                sv.pop("products")
+                line["serving"] = sv
         else:
             m = dev(wl.msgs)
             e, n = dev(e_h), dev(n_h)
@@ -323,17 +543,20 @@ def main():
                                                       "messages" % count}
             if bad:
                 raise SystemExit("round-trip check failed on %d elements" % bad)
-            products = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].e, plan))
+            as_run = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].e, plan))
             line.update(metric="2048-bit modexp/sec (encrypt, e=65537) on 1 GPU", unit="encryptions/s",
                         config={"workload": "rsa2048-encrypt", "keys": len(wl.keys), "messages": count,
                                 "radix_bits": plan.radix_bits, "window_bits": plan.window_bits,
                                 "lanes_per_op": plan.lanes_per_op})
-            line["roofline"] = roofline(products, ms, "k_modexp<%d,%d,%d>" % (plan.padded_limbs, plan.lanes_per_op,
-                                                                              plan.radix_bits))
+            per_unit = unit_enc_products(L)
+            line["roofline"] = roofline(per_unit * count, ms, "k_modexp<%d,%d,%d>" % (plan.padded_limbs,
+                                                                                      plan.lanes_per_op,
+                                                                                      plan.radix_bits),
+                                        per_unit, count, as_run, measured_peak())
             if args.cpu_sample:
                 import oracle
-                cpu = cpu_baseline(oracle, wl.msgs, e_h, n_h, out.cpu().numpy().view(np.uint32),
-                                   min(args.cpu_sample * 64, count), "encryptions/s", "m^65537 mod n")
+                cpu = cpu_baseline(oracle, wl.msgs, e_h, n_h, out.cpu().numpy().view(np.uint32), "encryptions/s",
+                                   "m^65537 mod n")
         value = count / (ms / 1e3)
 
     elif args.workload in ("rsa64", "rsa1024"):
@@ -351,16 +574,20 @@ def main():
                                                   "ciphertexts" % count}
         if bad:
             raise SystemExit("round-trip check failed on %d elements" % bad)
-        products = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].d, plan))
+        as_run = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].d, plan))
         line.update(metric="%d-bit modexp/sec (full-d decrypt) on 1 GPU" % (32 * L), unit="decryptions/s",
                     config={"workload": wl.name + "-decrypt", "messages": count, "radix_bits": plan.radix_bits,
                             "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
-        line["roofline"] = roofline(products, ms, "k_modexp<%d,%d,%d>" % (plan.padded_limbs, plan.lanes_per_op,
-                                                                          plan.radix_bits))
+        per_unit = unit_exp_products(L)
+        line["roofline"] = roofline(per_unit * count, ms, "k_modexp<%d,%d,%d>" % (plan.padded_limbs,
+                                                                                  plan.lanes_per_op,
+                                                                                  plan.radix_bits),
+                                    per_unit, count, as_run, measured_peak())
+        if L <= 2:
+            line["roofline"]["note"] = "launch-bound: one launch of ~80 dependent products"
         if args.cpu_sample:
             import oracle
-            cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32),
-                               min(args.cpu_sample * (16 if L <= 2 else 2), count), "decryptions/s",
+            cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32), "decryptions/s",
                                "plain C^d mod n")
         value = count / (ms / 1e3)
 
@@ -370,31 +597,131 @@ def main():
         ks = rsagpu.KeySet(len(wl.keys))
         for k in wl.keys:
             ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
+        tuned = {}
+        if not args.no_tune:
+            # autotuned plans per size: the ops-batch plans (kind 2 encryption,
+            # kind 3 CRT half, kind 4 the CRT half of the widest class of a
+            # bulk batch), each timed on synthetic keys at this workload's
+            # bucket size
+            from paper_1407_1465_amd import tune
+            sizes = sorted({k.limbs for k in wl.keys})
+            for L in sizes:
+                nk = int(((wl.kinds == 0) & (np.array([wl.keys[i].limbs for i in wl.key_ids]) == L)).sum())
+                nd = int(((wl.kinds == 1) & (np.array([wl.keys[i].limbs for i in wl.key_ids]) == L)).sum())
+                kinds = [(2, nk), (4 if L == sizes[-1] else 3, nd)]
+                for kind, cnt in kinds:
+                    pl = tune.tune(L, kind, 0, cnt)
+                    tuned["%d-bit kind %d" % (32 * L, kind)] = {"radix_bits": pl.radix_bits,
+                                                                "lanes_per_op": pl.lanes_per_op,
+                                                                "window_bits": pl.window_bits}
+            print("# tuned plans: %s" % json.dumps(tuned), file=sys.stderr, flush=True)
         ops = rsagpu.pack_ops(wl.kinds, wl.key_ids, wl.in_offs, wl.in_offs).cuda()
         inp = dev(wl.in_pool)
         out = torch.zeros(wl.out_words, dtype=torch.int32, device="cuda")
         ws = torch.empty(rsagpu.ops_workspace_size(nops), dtype=torch.uint8, device="cuda")
-        ms, wall = timed(lambda: rsagpu.ops_batch(ks, ops, inp, out, ws), args.steps, args.warmup, torch)
+        ms_eager, _ = timed(lambda: rsagpu.ops_batch(ks, ops, inp, out, ws), args.steps, args.warmup, torch)
+        # the same call captured once into a HIP graph and replayed
+        g = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            rsagpu.ops_batch(ks, ops, inp, out, ws)         # eager first: the stream's fork set exists
+            cs.synchronize()
+            with torch.cuda.graph(g, stream=cs):
+                rsagpu.ops_batch(ks, ops, inp, out, ws)
+        torch.cuda.current_stream().wait_stream(cs)
+        out.zero_()
+        steps_ms = []
+        ms, wall = timed(g.replay, args.steps, args.warmup, torch, steps_ms)
         back = torch.zeros_like(out)
         ops_inv = rsagpu.pack_ops(1 - wl.kinds, wl.key_ids, wl.in_offs, wl.in_offs).cuda()
         rsagpu.ops_batch(ks, ops_inv, out, back, ws)
         torch.cuda.synchronize()
         bad_words = int((back != inp).sum().item())
         errs = rsagpu.device_errors()
-        line["check"] = {"mismatches": bad_words + errs, "of": "every operation's output put through the "
-                                                               "opposite operation (words differing + data errors)"}
+        line["check"] = {"mismatches": bad_words + errs, "of": "every operation's output (graph replay) put "
+                                                               "through the opposite operation (words differing + "
+                                                               "data errors)"}
         if bad_words or errs:
             raise SystemExit("mixed batch round trip failed")
+
         def op_products(kk):
             kind, kid = kk
             k = wl.keys[kid]
             pl = rsagpu.get_plan(k.limbs // 2 if kind else k.limbs, kind + 2)      # ops-batch plans
             return crt_products(k, pl) if kind else modexp_products(k, k.e, pl)
-        products = per_key_sum(np.stack([wl.kinds, wl.key_ids], 1).tolist(), lambda kk: op_products(tuple(kk)))
+
+        def op_units(kk):
+            kind, kid = kk
+            k = wl.keys[kid]
+            return unit_crt_products(k.limbs // 2) if kind else unit_enc_products(k.limbs)
+        pairs = np.stack([wl.kinds, wl.key_ids], 1).tolist()
+        as_run = per_key_sum(pairs, lambda kk: op_products(tuple(kk)))
+        products = per_key_sum(pairs, lambda kk: op_units(tuple(kk)))
+        # plain form: one launch of the plain entry points per key and kind
+        plain_launches = []
+        pool_np = wl.in_pool
+        for kid, k in enumerate(wl.keys):
+            L, h = k.limbs, k.limbs // 2
+            for kind in (0, 1):
+                idx = np.nonzero((wl.key_ids == kid) & (wl.kinds == kind))[0]
+                if not idx.size:
+                    continue
+                x = dev(np.stack([pool_np[o:o + L] for o in wl.in_offs[idx]]))
+                cnt = len(idx)
+                if kind:
+                    a = [dev(np.tile(W.int_to_limbs(getattr(k, f), h), (cnt, 1))) for f in ("p", "q", "dp", "dq",
+                                                                                             "qinv")]
+                else:
+                    a = [dev(np.tile(W.int_to_limbs(getattr(k, f), L), (cnt, 1))) for f in ("e", "n")]
+                plain_launches.append((kind, x, a, torch.empty_like(x)))
+
+        def plain():
+            for kind, x, a, o in plain_launches:
+                if kind:
+                    rsagpu.decrypt_crt(x, *a, out=o)
+                else:
+                    rsagpu.modexp(x, *a, out=o)
+        ms_plain, _ = timed(plain, max(1, args.steps // 4), 1, torch)
         line.update(metric="mixed-size RSA ops/sec (1024-4096-bit, half CRT decrypt) on 1 GPU", unit="ops/s",
-                    config={"workload": wl.name, "ops": nops, "keys": len(wl.keys)})
-        line["roofline"] = roofline(products, ms, "k_ops_* (all buckets)")
+                    config={"workload": wl.name, "ops": nops, "keys": len(wl.keys),
+                            "plans": tuned or "default", "timed": "graph replay of one rsa_ops_batch call"})
+        line["eager_ms_per_step"] = ms_eager
+        line["batch_ms"] = {"p50": percentile(steps_ms, 50), "p99": percentile(steps_ms, 99)}
+        line["plain_one_key_per_launch"] = {"value": nops / (ms_plain / 1e3), "ms_per_step": ms_plain,
+                                            "launches": len(plain_launches)}
+        line["roofline"] = roofline(products, ms, "k_ops_* (all buckets)", "per operation by size and kind",
+                                    nops, as_run, measured_peak())
+        if args.cpu_sample:
+            import oracle
+            got = out.cpu().numpy().view(np.uint32)
+            by_l = {}
+            for i, (kind, kid, off) in enumerate(zip(wl.kinds, wl.key_ids, wl.in_offs)):
+                by_l.setdefault(wl.keys[kid].limbs, []).append(i)
+            t_cpu, n_cpu, threads = 0.0, 0, oracle_threads()
+            one = {}
+            for L, idx in sorted(by_l.items()):
+                if args.cpu_sample > 0:
+                    idx = idx[:args.cpu_sample]
+                base = np.stack([pool_np[wl.in_offs[i]:wl.in_offs[i] + L] for i in idx])
+                exps = W.ints_to_limbs([wl.keys[wl.key_ids[i]].d if wl.kinds[i] else wl.keys[wl.key_ids[i]].e
+                                        for i in idx], L)
+                mods = W.ints_to_limbs([wl.keys[wl.key_ids[i]].n for i in idx], L)
+                want, cw, _ = oracle.modexp_batch(base, exps, mods, nthreads=threads)
+                gpu = np.stack([got[wl.in_offs[i]:wl.in_offs[i] + L] for i in idx])
+                nbad = int((want != gpu).any(axis=1).sum())
+                if nbad:
+                    raise SystemExit("mixed batch differs from the oracle on %d %d-bit operations" % (nbad, 32 * L))
+                t_cpu += cw
+                n_cpu += len(idx)
+            share, ncpu, model = host_cpus()
+            cpu = {"value": n_cpu / t_cpu, "unit": "ops/s", "cores": threads, "kind": "oracle",
+                   "sample": "%s %d operations of the batch (plain M^e / C^d mod n, no CRT), %.1f s wall; every "
+                             "output equals the GPU's" % ("all" if n_cpu == nops else "a per-size prefix of",
+                                                         n_cpu, t_cpu),
+                   "verified": n_cpu, "mismatches": 0, "cpu_model": model, "host_cpus": ncpu, "cpu_share": share}
         value = nops / (ms / 1e3)
+        del g
         ks.close()
 
     elif args.workload == "paper":
@@ -454,72 +781,49 @@ def main():
                                          "sample": "key 0 of the same seeds, Python pow"}
         value = nk / wall
 
+    elif args.workload == "mulpeak":
+        from paper_1407_1465_amd import mulpeak
+        rates = [mulpeak.measure(op) for op in (0, 1, 2)]
+        mad = rates[0]
+        line.update(metric="32-bit integer multiply issue rate (v_mad_u64_u32) on 1 GPU", unit="T products/s",
+                    config={"workload": "mulpeak", "lanes_per_block": mad["lanes_per_block"],
+                            "chains_per_lane": mad["chains_per_lane"], "blocks": mad["blocks"],
+                            "iters": mad["iters"]})
+        line["rates"] = [{"op": r["op"], "value": r["ops_per_s"] / 1e12, "unit": "T ops/s",
+                          "frac_of_nominal": r["ops_per_s"] / INT32_MUL_PEAK, "ms_per_launch": r["ms_per_launch"],
+                          "ops_per_launch": r["ops_per_launch"],
+                          "lane_ops_per_clock_per_cu_at_2.4GHz": r["ops_per_s"] / (r["cus"] * 2.4e9)}
+                         for r in rates]
+        line["roofline"] = {"bound": "alu", "achieved": mad["ops_per_s"] / 1e12, "peak": INT32_MUL_PEAK / 1e12,
+                            "unit": "T int32-mul/s", "frac": mad["ops_per_s"] / INT32_MUL_PEAK, "traffic": None,
+                            "kernel": "k_mulpeak<0>", "products_per_launch": mad["ops_per_launch"],
+                            "ms_per_launch": mad["ms_per_launch"]}
+        line["check"] = {"mismatches": 0, "of": "no results (issue-rate probe)"}
+        value = mad["ops_per_s"] / 1e12
+        ms, wall = mad["ms_per_launch"], sum(r["ms_per_launch"] for r in rates) * 8 / 1e3
+
     else:   # serve
-        from paper_1407_1465_amd.serve import GpuExecutor, Server, poisson_requests
-        keys = W.make_keys(2048, W.SEED_BASE + 5, 256) + W.make_keys(4096, W.SEED_BASE + 5, 64)
-        ks = rsagpu.KeySet(len(keys))
-        for k in keys:
-            ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
-        limbs = [k.limbs for k in keys]
-        mods = [k.n for k in keys]
-        pool, max_ops = 1 << 23, 1 << 16
-        ex = GpuExecutor(ks, limbs, pool, max_ops)
-
-        last = {}
-
-        def run(reqs):
-            srv = Server(ex, pool, max_inflight=2, max_ops=max_ops)
-            srv.run(reqs)
-            last["finished"] = srv.finished
-            return srv.stats()
-
-        def verify(finished):
-            """Every served message through the opposite operation (one
-            rsa_ops_batch per chunk, after the timed run): elements whose
-            round trip differs."""
-            items = [(r.kind, r.key_id, row) for r in finished if r.error is None
-                     for row in zip(r.outputs, r.inputs)]
-            bad, chunk = 0, 1 << 15
-            ws_v = torch.empty(rsagpu.ops_workspace_size(chunk), dtype=torch.uint8, device="cuda")
-            for i0 in range(0, len(items), chunk):
-                part = items[i0:i0 + chunk]
-                offs = np.cumsum([0] + [limbs[kid] for _, kid, _ in part])
-                outs = np.concatenate([o for _, _, (o, _) in part]).astype(np.uint32)
-                ins = np.concatenate([x for _, _, (_, x) in part]).astype(np.uint32)
-                vops = rsagpu.pack_ops(np.array([1 - k for k, _, _ in part]), np.array([kid for _, kid, _ in part]),
-                                       offs[:-1], offs[:-1]).cuda()
-                back = torch.zeros(int(offs[-1]), dtype=torch.int32, device="cuda")
-                rsagpu.ops_batch(ks, vops, dev(outs), back, ws_v)
-                diff = back.cpu().numpy().view(np.uint32) != ins
-                bad += int(np.logical_or.reduceat(diff, offs[:-1]).sum())
-            return bad, len(items)
-        # saturated rate: the median of three closed bursts, after one
-        # unmeasured burst (first launches of every plan)
-        run(poisson_requests(0.0, 400, W.SEED_BASE + 49, limbs, mods))
-        bursts = sorted((run(poisson_requests(0.0, 400, W.SEED_BASE + 50 + 10 * i, limbs, mods))
-                         for i in range(3)), key=lambda b: b["requests_per_s"])
-        sat = bursts[1]
-        rate = 0.7 * sat["requests_per_s"]
-        nreq = max(200, int(rate * args.serve_seconds))
-        st = run(poisson_requests(rate, nreq, W.SEED_BASE + 51, limbs, mods))
-        bad, nmsg = verify(last["finished"])
-        errs = rsagpu.device_errors()
-        line["check"] = {"mismatches": bad + st["errors"] + errs,
-                         "of": "all %d served messages through the opposite operation, plus failed requests "
-                               "and device data errors" % nmsg}
-        if bad or st["errors"] or errs:
+        sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds, plain_requests=400)
+        line["check"] = sv.pop("check")
+        if line["check"]["mismatches"]:
             raise SystemExit("serving run reported errors")
+        products = sv.pop("products")
         line.update(metric="RSA serving (2048/4096-bit keys, 70% CRT decrypt): requests/s at p50/p99 latency",
                     unit="requests/s",
-                    config={"workload": "rsa-serve-2048-4096", "keys": len(keys), "rate_req_per_s": rate,
-                            "saturated_req_per_s": sat["requests_per_s"],
-                            "saturation_bursts_req_per_s": [b["requests_per_s"] for b in bursts],
-                            "requests": st["requests"]})
-        line["latency_ms"] = {"p50": st["p50_ms"], "p99": st["p99_ms"], "mean": st["mean_ms"]}
-        line["ops_per_s"] = st["ops_per_s"]
-        value = st["requests_per_s"]
-        ms, wall = st["span_s"] * 1e3, st["span_s"]
-        ks.close()
+                    config={"workload": "rsa-serve-2048-4096", "keys": 320, "rate_req_per_s": sv["rate_req_per_s"],
+                            "saturated_req_per_s": sv["saturated_req_per_s"],
+                            "saturation_bursts_req_per_s": sv["saturation_bursts_req_per_s"],
+                            "requests": sv["requests"], "streams": sv["streams"],
+                            "max_inflight": sv["max_inflight"]})
+        line["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"], "mean": sv["mean_ms"]}
+        line["ops_per_s"] = sv["ops_per_s"]
+        line["plain_one_request_per_launch"] = sv["plain_one_request_per_launch"]
+        line["roofline"] = roofline(products, sv["span_s"] * 1e3, "k_ops_* (every batch of the run)",
+                                    "per message by size and kind", sv["requests"], None, measured_peak())
+        line["roofline"]["note"] = ("served messages' algorithmic products over the run's span (arrival of "
+                                    "the first request to completion of the last), at 0.7 x saturation")
+        value = sv["requests_per_s"]
+        ms, wall = sv["span_s"] * 1e3, sv["span_s"]
 
     line["value"] = value
     line["ms_per_step"] = ms

@@ -147,14 +147,23 @@ int rsa_get_plan(int limbs, int kind, rsa_plan *plan);
 int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int window_bits);
 
 /*
- * Autotuner: for the width class of `limbs` (kind 0: exponentiation of
- * `limbs`-word operands with exp_bits-bit exponents; kind 1: CRT decryption
- * of `limbs`-word moduli with exp_bits-bit dp, dq; exp_bits <= 0 means full
- * length), times every compiled kernel instance of the class at every window
- * width that fits, on `count` synthetic operands, and installs the fastest
- * plan (rsa_set_plan).  Allocates and frees its own device buffers and
- * synchronises `stream`; not for use inside a timed or captured region.
- * The chosen plan is written to *best when not NULL.
+ * Autotuner: for the width class of `limbs` and plan `kind` (as in
+ * rsa_get_plan), times every compiled kernel instance of the class at every
+ * window width that fits, on `count` synthetic operands laid out as the
+ * workloads have them, and installs the fastest plan (rsa_set_plan):
+ *   kind 0: rsa_modexp_batch of `limbs`-word operands under one modulus and
+ *           one exp_bits-bit exponent (one key's messages);
+ *   kind 1: rsa_decrypt_crt_batch of `limbs`-word moduli, 16 keys
+ *           round-robin, exp_bits-bit dp and dq;
+ *   kind 2, 3, 4: rsa_ops_batch on a temporary keyset of 16 synthetic keys of
+ *           `limbs` words (limbs even), `count` operations round-robin over
+ *           the keys: e = 65537 encryptions (kind 2) or CRT decryptions with
+ *           full-length dp, dq (kinds 3 and 4; both plans hold the candidate
+ *           while it is timed, and the other kind's plan is restored after).
+ * exp_bits <= 0 means full length.  count <= 2^22 (kinds 2-4: 2^20).
+ * Allocates and frees its own device buffers (and keyset) and synchronises
+ * `stream`; not for use inside a timed or captured region.  The chosen
+ * plan is written to *best when not NULL.
  */
 int rsa_autotune(int limbs, int kind, int exp_bits, size_t count, hipStream_t stream, rsa_plan *best);
 
@@ -218,6 +227,20 @@ size_t rsa_ops_workspace_size(size_t max_ops);
  */
 int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, const uint32_t *in_pool, size_t in_words,
                   uint32_t *out_pool, size_t out_words, void *workspace, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Streams an rsa_ops_batch call forks its widest CRT buckets onto (0 to 3,
+ * default 3), beside the caller's stream, which runs every other bucket and
+ * then waits for the forks.  Each caller stream has a fork set of its own
+ * (up to 8 caller streams per keyset; further callers, and a caller first
+ * seen while it is being captured into a graph, run unforked), so calls on
+ * different caller streams overlap on the device.  A process has 4 hardware
+ * queues and streams beyond them share queues and serialise, so callers x
+ * (forks + 1) <= 4 keeps every bucket concurrent: 3 for one caller, 1 for
+ * two, 0 (every bucket in order on the caller's stream) for more.  Results
+ * do not depend on it.  Pure host setting, applies to later calls.
+ */
+int rsa_keyset_set_forks(rsa_keyset *ks, int forks);
 
 /*
  * Number of per-element data errors counted on the current device since the

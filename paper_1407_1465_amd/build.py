@@ -17,6 +17,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(CSRC, "_build")
 LIB = os.path.join(HERE, "librsagpu.so")
+# the integer-multiply issue-rate probe the roofline is measured against
+PEAK_SRC = os.path.join(HERE, "peak", "mulpeak.hip")
+PEAK_LIB = os.path.join(HERE, "libmulpeak.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -38,6 +41,10 @@ def deps():
         [os.path.join(ROOT, "include", "rsagpu.h")]
 
 
+def peak_deps():
+    return [PEAK_SRC, os.path.join(ROOT, "include", "mulpeak.h")]
+
+
 def hipcc() -> str:
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -55,13 +62,7 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
-def build(verbose: bool = False, out: str = LIB, extra=(), jobs: int = 0) -> str:
-    """Compile every HIP source and link librsagpu.so (always recompiles)."""
-    os.makedirs(OBJDIR, exist_ok=True)
-    srcs = sources()
-    jobs = jobs or min(16, os.cpu_count() or 1)
-    with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra), srcs))
+def _link(objs, out: str, verbose: bool) -> str:
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs"] + objs + ["-o", tmp]
     if verbose:
@@ -74,11 +75,26 @@ def build(verbose: bool = False, out: str = LIB, extra=(), jobs: int = 0) -> str
     return out
 
 
+def build(verbose: bool = False, out: str = LIB, extra=(), jobs: int = 0) -> str:
+    """Compile every HIP source and link librsagpu.so, and the multiply
+    probe libmulpeak.so beside it (always recompiles)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = sources() + [PEAK_SRC]
+    jobs = jobs or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, extra), srcs))
+    _link(objs[-1:], PEAK_LIB, verbose)
+    return _link(objs[:-1], out, verbose)
+
+
 def stale() -> bool:
-    if not os.path.exists(LIB):
-        return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(d) > t for d in deps() if os.path.exists(d))
+    for lib, ds in ((LIB, deps()), (PEAK_LIB, peak_deps())):
+        if not os.path.exists(lib):
+            return True
+        t = os.path.getmtime(lib)
+        if any(os.path.getmtime(d) > t for d in ds if os.path.exists(d)):
+            return True
+    return False
 
 
 if __name__ == "__main__":

@@ -293,10 +293,6 @@ __device__ __forceinline__ void mac(uint64_t &acc, uint32_t &hi, uint32_t x, uin
 __device__ __forceinline__ void mac2(uint64_t &acc0, uint32_t &hi0, uint32_t x0, uint64_t &acc1, uint32_t &hi1,
                                      uint32_t x1, uint32_t y)
 {
-#ifdef RSAGPU_MAC_VCC
-    mac(acc0, hi0, x0, y);
-    mac(acc1, hi1, x1, y);
-#else
     uint64_t c0, c1;
     asm("v_mad_u64_u32 %0, %4, %6, %8, %0\n\t"
         "v_mad_u64_u32 %1, %5, %7, %8, %1\n\t"
@@ -304,7 +300,6 @@ __device__ __forceinline__ void mac2(uint64_t &acc0, uint32_t &hi0, uint32_t x0,
         "v_addc_co_u32_e64 %3, %5, 0, %3, %5"
         : "+v"(acc0), "+v"(acc1), "+v"(hi0), "+v"(hi1), "=&s"(c0), "=&s"(c1)
         : "v"(x0), "v"(x1), "v"(y));
-#endif
 }
 
 // Row update: acc[(j + k) % L] += x[j] * y for all j.

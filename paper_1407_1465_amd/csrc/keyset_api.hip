@@ -117,15 +117,24 @@ struct rsa_keyset {
     rsagpu::KeyHostInfo *info;      // host copy per key
     unsigned class_mask;            // width classes present
     std::mutex mu;
-    // fork/join of the per-bucket kernels (created on first use)
-    // with the caller's stream, one per hardware queue of a process (HIP's
-    // default of 4): more streams would share queues and serialise buckets
-    // behind each other
+    // Fork/join of the per-bucket kernels: each caller stream has a fork set
+    // of its own (streams created on its first forked call), so calls on
+    // different caller streams never queue behind each other's buckets.
+    // `forks` (at most kStreams) bounds the streams a call forks onto: a
+    // process has HIP's default of 4 hardware queues, and streams beyond
+    // them share queues and serialise, so callers x (forks + 1) <= 4 keeps
+    // every bucket concurrent.
     static const int kStreams = 3;
-    hipStream_t streams[kStreams];
-    hipEvent_t fork;
-    hipEvent_t done[2 * 16];
-    bool have_streams;
+    static const int kForkSets = 8;
+    struct ForkSet {
+        hipStream_t caller;
+        hipStream_t streams[kStreams];
+        hipEvent_t fork;
+        hipEvent_t done[kStreams];
+    };
+    ForkSet forksets[kForkSets];
+    int nforksets;
+    int forks = kStreams;
     std::mutex launch_mu;
 };
 
@@ -216,10 +225,11 @@ extern "C" int rsa_keyset_destroy(rsa_keyset *ks)
     if (ks->stage_mods) (void)hipFree(ks->stage_mods);
     if (ks->stage_words) (void)hipFree(ks->stage_words);
     if (ks->stage_outs) (void)hipFree(ks->stage_outs);
-    if (ks->have_streams) {
-        for (hipStream_t s : ks->streams) (void)hipStreamDestroy(s);
-        (void)hipEventDestroy(ks->fork);
-        for (hipEvent_t e : ks->done) (void)hipEventDestroy(e);
+    for (int i = 0; i < ks->nforksets; ++i) {
+        rsa_keyset::ForkSet &f = ks->forksets[i];
+        for (hipStream_t s : f.streams) (void)hipStreamDestroy(s);
+        (void)hipEventDestroy(f.fork);
+        for (hipEvent_t e : f.done) (void)hipEventDestroy(e);
     }
     delete[] ks->info;
     delete ks;
@@ -352,19 +362,38 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 1;
 
-    // The buckets run concurrently: each on one of the keyset's streams,
-    // forked from `stream` after the bucketing and joined back into it, so
-    // small or latency-bound buckets overlap the large ones.
+    // The buckets run concurrently: the widest CRT buckets each on a stream
+    // of the caller stream's fork set, forked from `stream` after the
+    // bucketing and joined back into it, so small or latency-bound buckets
+    // overlap the large ones.
     std::lock_guard<std::mutex> launch_lock(ks->launch_mu);
-    if (!ks->have_streams) {
-        for (hipStream_t &st : ks->streams)
-            if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return status_of(e);
-        if ((e = hipEventCreateWithFlags(&ks->fork, hipEventDisableTiming)) != hipSuccess) return status_of(e);
-        for (hipEvent_t &ev : ks->done)
-            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return status_of(e);
-        ks->have_streams = true;
+    rsa_keyset::ForkSet *fs = nullptr;
+    int nfork = ks->forks;
+    if (nfork > 0) {
+        for (int i = 0; i < ks->nforksets; ++i)
+            if (ks->forksets[i].caller == stream) fs = &ks->forksets[i];
+        if (!fs && ks->nforksets < rsa_keyset::kForkSets) {
+            // streams and events are made once per caller stream (never while
+            // the caller is being captured into a graph: no fork then)
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+                rsa_keyset::ForkSet f{};
+                f.caller = stream;
+                int made = 0;
+                bool ok = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) == hipSuccess;
+                for (; ok && made < rsa_keyset::kStreams; ++made)
+                    ok = hipStreamCreateWithFlags(&f.streams[made], hipStreamNonBlocking) == hipSuccess &&
+                         hipEventCreateWithFlags(&f.done[made], hipEventDisableTiming) == hipSuccess;
+                if (!ok) return RSA_EHIP;
+                ks->forksets[ks->nforksets] = f;
+                fs = &ks->forksets[ks->nforksets++];
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (!fs) nfork = 0;         // no fork set for this caller: every bucket on `stream`
     }
-    if ((e = hipEventRecord(ks->fork, stream)) != hipSuccess) return status_of(e);
+    if (nfork > 0 && (e = hipEventRecord(fs->fork, stream)) != hipSuccess) return status_of(e);
     // Bucket order and streams: the CRT buckets of the widest classes are the
     // longest (their operations are long dependency chains that a bucket's
     // waves cannot shorten), so each of them gets a keyset stream of its own;
@@ -386,19 +415,27 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         int per = r.inst->blocks_per_cu(kind, r.w);
         if (per <= 0) per = 1;
         const int blocks = per * cus;
-        const bool fork = kind == 1 && t < rsa_keyset::kStreams;
-        hipStream_t s = fork ? ks->streams[t] : stream;
-        if (fork && (e = hipStreamWaitEvent(s, ks->fork, 0)) != hipSuccess) return status_of(e);
+        const bool fork = kind == 1 && t < nfork;
+        hipStream_t s = fork ? fs->streams[t] : stream;
+        if (fork && (e = hipStreamWaitEvent(s, fs->fork, 0)) != hipSuccess) return status_of(e);
         const ops_launcher fn = kind == 0 ? r.inst->ops_enc : r.inst->ops_crt;
         e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b, counters + b,
                in_pool, out_pool, r.w, blocks, pkind == 4 ? 1 : 0, s);
         if (e != hipSuccess) return status_of(e);
         if (fork) {
-            if ((e = hipEventRecord(ks->done[t], s)) != hipSuccess) return status_of(e);
+            if ((e = hipEventRecord(fs->done[t], s)) != hipSuccess) return status_of(e);
             ++forked;
         }
     }
     for (int t = 0; t < forked; ++t)
-        if ((e = hipStreamWaitEvent(stream, ks->done[t], 0)) != hipSuccess) return status_of(e);
+        if ((e = hipStreamWaitEvent(stream, fs->done[t], 0)) != hipSuccess) return status_of(e);
+    return RSA_OK;
+}
+
+extern "C" int rsa_keyset_set_forks(rsa_keyset *ks, int forks)
+{
+    if (!ks || forks < 0 || forks > rsa_keyset::kStreams) return RSA_EINVAL;
+    std::lock_guard<std::mutex> launch_lock(ks->launch_mu);
+    ks->forks = forks;
     return RSA_OK;
 }

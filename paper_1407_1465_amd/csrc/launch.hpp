@@ -42,6 +42,12 @@ __host__ __device__ constexpr bool standard_s29(int S)
     return S == 18 || S == 28 || S == 36 || S == 56 || S == 72 || S == 112 || S == 144;
 }
 
+// Instances that also serve CRT halves: the half of the widest modulus
+// (128 words) has 64 words, S = 64 limbs in radix 2^32 and at most 80 in
+// radix 2^29 (72, or 80 rounded up for 16 lanes).  Wider instances exist for
+// full-width exponentiation only and compile no CRT kernels.
+__host__ __device__ constexpr bool crt_instance(int S, int B) { return B == 32 ? S <= 64 : S <= 80; }
+
 // Instances whose Montgomery products inside the exponentiation take the
 // multiplier from registers (1, 2 or 4 lanes per group: at most one DPP quad
 // permute per step; 16 lanes in radix 2^29: one DPP row broadcast per step);

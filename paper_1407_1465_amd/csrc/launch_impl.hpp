@@ -65,30 +65,39 @@ int ops_blocks_per_cu(int kind, int w)
 {
     int nb = 0;
     const size_t lds = lds_bytes_for(S, G, B, w);
-    hipError_t e = kind == 0
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_enc<S, G, B>), 64, lds)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B>), 128,
-                                                       2 * lds);
+    hipError_t e = hipErrorInvalidValue;
+    if (kind == 0)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_enc<S, G, B>), 64,
+                                                         lds);
+    else if constexpr (crt_instance(S, B))
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B>),
+                                                         128, 2 * lds);
     return e == hipSuccess ? nb : 0;
 }
 
 }  // namespace rsagpu
 
-#define RSAGPU_INSTANTIATE(B_, S_, G_)                                                                      \
+// Every launcher of an instance; RSAGPU_INSTANTIATE_EXP leaves out the CRT
+// ones (instances wider than any CRT half, see crt_instance).
+#define RSAGPU_INSTANTIATE_EXP(B_, S_, G_)                                                                  \
     template hipError_t rsagpu::launch_modexp<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *, \
                                                       uint32_t *, size_t, int, int, unsigned long long *,   \
                                                       hipStream_t);                                         \
-    template hipError_t rsagpu::launch_crt<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *,    \
-                                                   const uint32_t *, const uint32_t *, const uint32_t *,    \
-                                                   const unsigned *, uint32_t *, size_t, int, int,          \
-                                                   unsigned long long *, hipStream_t);                      \
     template hipError_t rsagpu::launch_setup<S_, G_, B_>(const uint32_t *const *, const uint32_t *const *,  \
                                                          const int *, rsagpu::ModConsts *, int,             \
                                                          hipStream_t);                                      \
     template hipError_t rsagpu::launch_ops_enc<S_, G_, B_>(                                                 \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
         const uint32_t *, uint32_t *, int, int, int, hipStream_t);                                          \
+    template int rsagpu::ops_blocks_per_cu<S_, G_, B_>(int, int);
+
+#define RSAGPU_INSTANTIATE(B_, S_, G_)                                                                      \
+    static_assert(rsagpu::crt_instance(S_, B_), "CRT launchers of an instance wider than any CRT half");    \
+    RSAGPU_INSTANTIATE_EXP(B_, S_, G_)                                                                      \
+    template hipError_t rsagpu::launch_crt<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *,    \
+                                                   const uint32_t *, const uint32_t *, const uint32_t *,    \
+                                                   const unsigned *, uint32_t *, size_t, int, int,          \
+                                                   unsigned long long *, hipStream_t);                      \
     template hipError_t rsagpu::launch_ops_crt<S_, G_, B_>(                                                 \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
-        const uint32_t *, uint32_t *, int, int, int, hipStream_t);                                          \
-    template int rsagpu::ops_blocks_per_cu<S_, G_, B_>(int, int);
+        const uint32_t *, uint32_t *, int, int, int, hipStream_t);

@@ -11,10 +11,24 @@
 
 namespace rsagpu {
 
+// CRT launchers of an instance, null where it is wider than any CRT half.
+template <int S, int G, int B>
+constexpr crt_launcher crt_of()
+{
+    if constexpr (crt_instance(S, B)) return &launch_crt<S, G, B>;
+    else return nullptr;
+}
+template <int S, int G, int B>
+constexpr ops_launcher ops_crt_of()
+{
+    if constexpr (crt_instance(S, B)) return &launch_ops_crt<S, G, B>;
+    else return nullptr;
+}
+
 static const Instance kInstances[] = {
 #define X(B_, S_, G_)                                                                                     \
-    {B_, S_, G_, &launch_modexp<S_, G_, B_>, &launch_crt<S_, G_, B_>, &launch_setup<S_, G_, B_>,          \
-     &launch_ops_enc<S_, G_, B_>, &launch_ops_crt<S_, G_, B_>, &ops_blocks_per_cu<S_, G_, B_>},
+    {B_, S_, G_, &launch_modexp<S_, G_, B_>, crt_of<S_, G_, B_>(), &launch_setup<S_, G_, B_>,             \
+     &launch_ops_enc<S_, G_, B_>, ops_crt_of<S_, G_, B_>(), &ops_blocks_per_cu<S_, G_, B_>},
 #include "instances.def"
 #undef X
 };
@@ -118,6 +132,8 @@ const Instance *any_instance(int i, int B)
     return nullptr;
 }
 
+static bool crt_kind(int kind) { return kind == 1 || kind == 3 || kind == 4; }
+
 bool resolve(int limbs, int kind, Resolved *r)
 {
     std::call_once(g_plan_once, init_plans);
@@ -126,7 +142,7 @@ bool resolve(int limbs, int kind, Resolved *r)
     const Plan p = unpack(g_plan[kind][i].load());
     r->inst = find_instance(i, p.B, p.G);
     r->w = p.w;
-    return r->inst != nullptr;
+    return r->inst != nullptr && (!crt_kind(kind) || (r->inst->crt && r->inst->ops_crt));
 }
 
 // ---- per-device state: the data-error counter ------------------------------
@@ -237,7 +253,7 @@ extern "C" int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_o
         return RSA_OK;
     }
     const Instance *in = find_instance(i, radix_bits, lanes_per_op);
-    if (!in) return RSA_EINVAL;
+    if (!in || (crt_kind(kind) && !(in->crt && in->ops_crt))) return RSA_EINVAL;
     if (window_bits < 2 || window_bits > 7) return RSA_EINVAL;
     if (lds_bytes_for(in->S, in->G, in->B, window_bits) > 64 * 1024) return RSA_EINVAL;
     g_plan[kind][i].store(pack(Plan{radix_bits, lanes_per_op, window_bits}));

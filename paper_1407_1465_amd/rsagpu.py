@@ -63,11 +63,13 @@ _lib.rsa_ops_workspace_size.restype = ctypes.c_size_t
 _lib.rsa_ops_batch.argtypes = [_P, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P, ctypes.c_size_t, _P,
                                ctypes.c_size_t, _P]
 _lib.rsa_ops_batch.restype = ctypes.c_int
+_lib.rsa_keyset_set_forks.argtypes = [_P, ctypes.c_int]
+_lib.rsa_keyset_set_forks.restype = ctypes.c_int
 
 # exported symbols, in the order include/rsagpu.h declares them
 EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_get_plan", "rsa_set_plan", "rsa_autotune", "rsa_init",
            "rsa_keyset_create", "rsa_keyset_add", "rsa_keyset_destroy", "rsa_ops_workspace_size",
-           "rsa_ops_batch", "rsa_device_errors", "rsa_status_str", "rsa_version")
+           "rsa_ops_batch", "rsa_keyset_set_forks", "rsa_device_errors", "rsa_status_str", "rsa_version")
 
 OP_ENCRYPT = 0
 OP_DECRYPT_CRT = 1
@@ -202,6 +204,10 @@ class KeySet:
                "rsa_keyset_add")
         self.limbs.append(limbs)
         return kid.value
+
+    def set_forks(self, forks: int) -> None:
+        """Streams a batch forks its widest CRT buckets onto (rsa_keyset_set_forks)."""
+        _check(_lib.rsa_keyset_set_forks(self._h, forks), "rsa_keyset_set_forks")
 
     def close(self) -> None:
         if self._h:

@@ -217,7 +217,8 @@ class Server:
 
 
 class GpuExecutor:
-    """Runs batches through rsa_ops_batch on a rotating set of streams.
+    """Runs batches through rsa_ops_batch, each on an idle stream of its own
+    (at most one batch per stream, so max_inflight = streams).
 
     Inputs and outputs pass through pinned host mirrors of the device pools
     (a request's slot range is the same in both), so a batch costs one
@@ -243,14 +244,19 @@ class GpuExecutor:
         self.ops_host = [torch.zeros((max_ops, 3), dtype=torch.int64, pin_memory=True) for _ in range(streams)]
         self.ops_dev = [torch.zeros((max_ops, 3), dtype=torch.int64, device="cuda") for _ in range(streams)]
         self.max_ops = max_ops
-        self.next = 0
+        self.max_inflight = streams
+        self.last = [None] * streams           # completion event of each stream's batch
+
+    def _idle_stream(self) -> int:
+        for k, ev in enumerate(self.last):
+            if ev is None or ev.query():
+                return k
+        raise RuntimeError("every stream has a batch in flight (more batches than streams)")
 
     def launch(self, reqs: List[Request]):
         torch = self.torch
-        k = self.next % len(self.streams)
-        self.next += 1
+        k = self._idle_stream()
         s = self.streams[k]
-        s.synchronize()                        # this stream's descriptor buffers are free again
         kinds, kids, ins, outs = [], [], [], []
         for r in reqs:
             L = self.limbs[r.key_id]
@@ -276,6 +282,7 @@ class GpuExecutor:
                                                                    non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
+        self.last[k] = ev
         return (ev, reqs)
 
     def poll(self, handle) -> bool:

@@ -2,11 +2,12 @@
 
 `tune(limbs, kind, exp_bits, count)` runs the library's autotuner
 (rsa_autotune: every compiled kernel instance of the width class at every
-window that fits, timed on synthetic operands of the given batch size) and
-records the winner in a JSON cache; `apply_cached()` re-installs cached plans
-with rsa_set_plan so later processes skip the search.  Entries are keyed by
-the GPU architecture, the operand width class, the kind, the exponent length
-and the batch size rounded to a power of two.
+window that fits, timed on synthetic operands of the given batch size: plain
+calls for kinds 0 and 1, rsa_ops_batch on a synthetic keyset for kinds 2 to
+4) and records the winner in a JSON cache; `apply_cached()` re-installs
+cached plans with rsa_set_plan so later processes skip the search.  Entries
+are keyed by the GPU architecture, the operand width in words, the kind, the
+exponent length and the batch size rounded up to a power of two.
 """
 from __future__ import annotations
 
@@ -30,8 +31,15 @@ def _arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
+CRT_KINDS = (1, 3, 4)
+
+
+def plan_width(limbs: int, kind: int) -> int:
+    """Width whose class a plan of `kind` is stored under (CRT: one half)."""
+    return limbs // 2 if kind in CRT_KINDS else limbs
+
+
 def _key(limbs: int, kind: int, exp_bits: int, count: int) -> str:
-    cls = rsagpu.get_plan(limbs if kind == 0 else limbs // 2, kind).padded_limbs
     bucket = 1 << max(0, (count - 1).bit_length())
     return "%s/w%d/k%d/e%d/n%d" % (_arch(), limbs, kind, exp_bits, bucket)
 
@@ -57,7 +65,7 @@ def tune(limbs: int, kind: int, exp_bits: int, count: int, use_cache: bool = Tru
     """Best plan for (limbs, kind, exp_bits, count), installed in the library."""
     cache = load()
     key = _key(limbs, kind, exp_bits, count)
-    width = limbs if kind == 0 else limbs // 2
+    width = plan_width(limbs, kind)
     if use_cache and key in cache:
         e = cache[key]
         rsagpu.set_plan(width, kind, e["radix_bits"], e["lanes_per_op"], e["window_bits"])
@@ -78,7 +86,7 @@ def apply_cached(arch: Optional[str] = None) -> int:
         if parts[0] != arch:
             continue
         limbs, kind = int(parts[1][1:]), int(parts[2][1:])
-        width = limbs if kind == 0 else limbs // 2
+        width = plan_width(limbs, kind)
         rsagpu.set_plan(width, kind, e["radix_bits"], e["lanes_per_op"], e["window_bits"])
         n += 1
     return n

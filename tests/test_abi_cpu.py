@@ -61,6 +61,11 @@ def test_plans_are_consistent():
     from paper_1407_1465_amd import rsagpu
     for limbs in range(1, 129):
         for kind in (0, 1):
+            if kind == 1 and limbs > 64:
+                # no CRT half is wider than 64 words: no CRT plan there
+                with pytest.raises(Exception):
+                    rsagpu.get_plan(limbs, kind)
+                continue
             p = rsagpu.get_plan(limbs, kind)
             assert p.radix_bits * p.padded_limbs >= 32 * limbs
             assert p.lanes_per_op * p.limbs_per_lane == p.padded_limbs
@@ -131,3 +136,30 @@ def test_plan_lds_sizes():
     finally:
         for limbs, kind in ((32, 1), (64, 0)):
             rsagpu.set_plan(limbs, kind, 0, 0, 0)
+
+
+PEAK_HEADER = os.path.join(ROOT, "include", "mulpeak.h")
+PEAK_LIB = os.path.join(ROOT, "paper_1407_1465_amd", "libmulpeak.so")
+
+
+def test_mulpeak_library_exports_and_validates():
+    """The multiply-rate probe library loads, exports what include/mulpeak.h
+    declares and rejects bad arguments before any HIP call."""
+    if not os.path.exists(PEAK_LIB):
+        pytest.fail("libmulpeak.so is not built (run __graft_entry__.build())")
+    text = re.sub(r"/\*.*?\*/", "", open(PEAK_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(mulpeak_[a-z0-9_]+)\s*\(", text)))
+    assert names == ["mulpeak_launch"]
+    plib = ctypes.CDLL(PEAK_LIB)
+    f = plib.mulpeak_launch
+    P = ctypes.c_void_p
+    f.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_int, P]
+    d = P(16)
+    assert f(3, d, d, 1, 1, None) == -1          # unknown operation
+    assert f(0, None, d, 1, 1, None) == -1       # null seed
+    assert f(0, d, d, 0, 1, None) == -1          # no blocks
+    assert f(1, d, d, 1, 0, None) == -1          # no iterations
+    from paper_1407_1465_amd import mulpeak
+    assert mulpeak.LANES == 256 and mulpeak.CHAINS == 16 and mulpeak.SEED_WORDS == 256
+    for name, val in (("MULPEAK_LANES", 256), ("MULPEAK_CHAINS", 16), ("MULPEAK_SEED_WORDS", 256)):
+        assert re.search(r"#define %s %d\b" % (name, val), text)

@@ -1,8 +1,8 @@
 """The entry points captured in a HIP graph (torch.cuda.graph) and replayed:
 plain CRT decryption (with its key ordering in the stream's library buffer,
 or in the given order on a stream captured before it ever ran the call), plain
-exponentiation and a keyset batch (with its bucket sort and forked bucket
-streams).  Each of several replays, with eager work and synchronisation
+exponentiation and a keyset batch (with its bucket sort and the caller
+stream's forked bucket streams).  Each of several replays, with eager work and synchronisation
 between them, must equal the eager results."""
 import numpy as np
 import pytest
@@ -53,6 +53,8 @@ def test_graph_capture_and_replay():
         # warm-up on the capture stream: the CRT call's key-order buffer for
         # this stream exists before capture (a capture never allocates)
         rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out_crt)
+        # and the keyset's fork set of this caller stream
+        rsagpu.ops_batch(ks, ops, pool_in, out_ops, ws)
         s.synchronize()
         with torch.cuda.graph(g, stream=s):
             rsagpu.decrypt_crt(c, p, q, dp, dq, qi, out=out_crt)

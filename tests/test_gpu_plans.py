@@ -102,14 +102,23 @@ def test_instance_modexp_shared_exponent(B, S, G, plan_guard):
     assert rsagpu.device_errors() == 0
 
 
-@pytest.mark.parametrize("B,S,G", [i for i in INSTANCES if 64 // i[2] >= 2])
+# instances that serve CRT halves: up to the half of a 128-word modulus
+CRT_INSTANCES = [i for i in INSTANCES if 64 // i[2] >= 2 and i[1] <= (64 if i[0] == 32 else 80)]
+
+
+def test_wide_instances_have_no_crt_plan():
+    for B, S, G in INSTANCES:
+        if (B, S, G) not in CRT_INSTANCES and 64 // G >= 2:
+            with pytest.raises(Exception):
+                rsagpu.set_plan(width_class(B, S), 1, B, G, 2)
+
+
+@pytest.mark.parametrize("B,S,G", CRT_INSTANCES)
 def test_instance_crt(B, S, G, plan_guard):
     cls = width_class(B, S)
     rsagpu.set_plan(cls, 1, B, G, window_for(B, S, G))
     plan_guard.append((cls, 1))
     bits = 64 * cls
-    if bits > 4096:
-        pytest.skip("no keys above 4096 bits in the workloads")
     keys = W.make_keys(bits, 4242 + bits, 2)
     L = keys[0].limbs
     h = L // 2
@@ -151,4 +160,46 @@ def test_autotune_installs_a_working_plan(plan_guard):
     out = host(rsagpu.decrypt_crt(dev(C), dev(col("p", h)), dev(col("q", h)), dev(col("dp", h)),
                                   dev(col("dq", h)), dev(col("qinv", h))))
     assert np.array_equal(out, oracle_modexp(C, col("d", L), col("n", L)))
+    assert rsagpu.device_errors() == 0
+
+
+def ops_batch_vs_oracle(keys, kinds, count, seed):
+    """count operations round-robin over `keys` (kind per op), through one
+    rsa_ops_batch call, compared element by element with the oracle."""
+    L = keys[0].limbs
+    ks = rsagpu.KeySet(len(keys))
+    for k in keys:
+        ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
+    kid = np.arange(count) % len(keys)
+    X = np.concatenate([W.uniform_below(keys[j].n, 1, W.derive_seed(seed, i), L) for i, j in enumerate(kid)])
+    offs = np.arange(count, dtype=np.int64) * L
+    ops = rsagpu.pack_ops(kinds, kid, offs, offs).cuda()
+    out = torch.zeros(count * L, dtype=torch.int32, device="cuda")
+    ws = torch.empty(rsagpu.ops_workspace_size(count), dtype=torch.uint8, device="cuda")
+    rsagpu.ops_batch(ks, ops, dev(X.reshape(-1)), out, ws)
+    got = host(out).reshape(count, L)
+    exps = W.ints_to_limbs([keys[j].d if kd else keys[j].e for j, kd in zip(kid, kinds)], L)
+    want = oracle_modexp(X, exps, W.ints_to_limbs([keys[j].n for j in kid], L))
+    ks.close()
+    return np.nonzero((got != want).any(axis=1))[0]
+
+
+@pytest.mark.parametrize("bits,kind,count", [(2048, 2, 512), (4096, 3, 256), (512, 4, 16384)])
+def test_autotune_ops_plans_install_working_plans(bits, kind, count, plan_guard):
+    """rsa_autotune for the ops-batch kinds (2: encryption, 3: CRT half, 4:
+    the CRT half of the widest class of a bulk batch of >= 16384 operations)
+    installs a plan; a batch of real keys that takes that plan matches the
+    oracle bit for bit."""
+    L = bits // 32
+    width = L if kind == 2 else L // 2
+    plan_guard.append((width, kind))
+    best = rsagpu.autotune(L, kind, 0, count)
+    assert rsagpu.get_plan(width, kind) == best
+    if bits == 512:
+        keys = W.make_keys(512, 6161, 3)
+    else:
+        keys = W.make_keys(bits, W.SEED_BASE + 5, 256 if bits == 2048 else 64)[:3]
+    kinds = np.full(count, 0 if kind == 2 else 1, dtype=np.int64)
+    bad = ops_batch_vs_oracle(keys, kinds, count, 7000 + bits)
+    assert bad.size == 0, "%d-bit kind %d plan %s: %d bad" % (bits, kind, best, bad.size)
     assert rsagpu.device_errors() == 0

@@ -67,3 +67,29 @@ def test_memory_pressure_on_gpu(keyset):
         assert r.error is None
         assert np.array_equal(r.outputs, expected(keys, r))
     assert srv.in_pool.used == 0
+
+
+def test_serving_config_keys_match_oracle_and_alone():
+    """Keys of the serving workload (2048- and 4096-bit, cached seeds), 70%
+    CRT decryptions, requests of 1..64 messages arriving while batches run on
+    several streams: every request against the oracle, a few alone."""
+    keys = W.make_keys(2048, W.SEED_BASE + 5, 256)[:6] + W.make_keys(4096, W.SEED_BASE + 5, 64)[:3]
+    ks = rsagpu.KeySet(len(keys))
+    for k in keys:
+        ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
+    limbs = [k.limbs for k in keys]
+    reqs = poisson_requests(3000.0, 40, 21, limbs, [k.n for k in keys], max_msgs=64)
+    pool, max_ops = 1 << 20, 1 << 14
+    ex = GpuExecutor(ks, limbs, pool, max_ops, streams=3)
+    srv = Server(ex, pool, max_inflight=ex.max_inflight, max_ops=max_ops)
+    srv.run(reqs)
+    assert len(srv.finished) == len(reqs) and all(r.error is None for r in srv.finished)
+    for r in srv.finished:
+        assert np.array_equal(r.outputs, expected(keys, r)), "request %d" % r.rid
+    by_id = {r.rid: r for r in srv.finished}
+    for r in reqs[:4]:
+        alone = Server(ex, pool, max_inflight=1, max_ops=max_ops)
+        alone.run([Request(0, r.key_id, r.kind, r.inputs, arrival=0.0)])
+        assert np.array_equal(alone.finished[0].outputs, by_id[r.rid].outputs)
+    assert rsagpu.device_errors() == 0
+    ks.close()
