@@ -317,7 +317,7 @@ def cpu_baseline(oracle, base, exp, mod, gpu_out, unit, what, count=None, prefix
             "one_thread": {"value": k / wall1, "unit": unit, "sample": "first %d elements" % k}}
 
 
-def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0):
+def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0, streams=2, forks=1):
     """Serving run (256 x 2048-bit + 64 x 4096-bit resident keys, 70% CRT
     decryptions, 1..256 messages per request): the saturated request rate as
     the median of three closed bursts of 400 requests (after one unmeasured
@@ -334,7 +334,7 @@ def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0):
     limbs = [k.limbs for k in keys]
     mods = [k.n for k in keys]
     pool, max_ops = 1 << 23, 1 << 16
-    ex = GpuExecutor(ks, limbs, pool, max_ops)
+    ex = GpuExecutor(ks, limbs, pool, max_ops, streams=streams, forks=forks)
     last = {}
 
     def run(reqs):
@@ -380,7 +380,7 @@ def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0):
            "mean_ms": st["mean_ms"], "ops_per_s": st["ops_per_s"], "requests": st["requests"],
            "rate_req_per_s": rate, "saturated_req_per_s": sat["requests_per_s"],
            "saturation_bursts_req_per_s": [b["requests_per_s"] for b in bursts], "span_s": st["span_s"],
-           "streams": len(ex.streams), "max_inflight": ex.max_inflight,
+           "streams": len(ex.streams), "forks": forks, "max_inflight": ex.max_inflight,
            "check": {"mismatches": bad + st["errors"] + errs,
                      "of": "all %d served messages through the opposite operation, plus failed requests "
                            "and device data errors" % nmsg},
@@ -432,6 +432,9 @@ def main():
                     help="length of the Poisson serving run (serve: 8 s; the default workload adds a 3 s run "
                          "for its request latencies, 0 leaves it out)")
     ap.add_argument("--no-tune", action="store_true", help="mixed: keep the default plans (no autotuning)")
+    ap.add_argument("--serve-streams", type=int, default=2, help="serving: executor streams (batches in flight)")
+    ap.add_argument("--serve-forks", type=int, default=1,
+                    help="serving: streams each batch forks its widest CRT buckets onto")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference "
                          "dispatch for hardware traffic counters)")
@@ -522,7 +525,8 @@ def main():
                                    "plain C^d mod n (no CRT)",
                                    None if args.cpu_sample < 0 else min(args.cpu_sample, count))
             if args.serve_seconds > 0:
-                sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds)
+                sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds, streams=args.serve_streams,
+                               forks=args.serve_forks)
                 if sv["check"]["mismatches"]:
                     raise SystemExit("serving run reported errors")
                 line["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"],
@@ -803,7 +807,8 @@ def main():
         ms, wall = mad["ms_per_launch"], sum(r["ms_per_launch"] for r in rates) * 8 / 1e3
 
     else:   # serve
-        sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds, plain_requests=400)
+        sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds, plain_requests=400, streams=args.serve_streams,
+                       forks=args.serve_forks)
         line["check"] = sv.pop("check")
         if line["check"]["mismatches"]:
             raise SystemExit("serving run reported errors")
@@ -813,7 +818,7 @@ def main():
                     config={"workload": "rsa-serve-2048-4096", "keys": 320, "rate_req_per_s": sv["rate_req_per_s"],
                             "saturated_req_per_s": sv["saturated_req_per_s"],
                             "saturation_bursts_req_per_s": sv["saturation_bursts_req_per_s"],
-                            "requests": sv["requests"], "streams": sv["streams"],
+                            "requests": sv["requests"], "streams": sv["streams"], "forks": sv["forks"],
                             "max_inflight": sv["max_inflight"]})
         line["latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"], "mean": sv["mean_ms"]}
         line["ops_per_s"] = sv["ops_per_s"]

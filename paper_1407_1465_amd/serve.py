@@ -225,12 +225,17 @@ class GpuExecutor:
     descriptor upload, one copy per request each way and one library call."""
 
     def __init__(self, keyset, limbs_of_key: Sequence[int], pool_words: int, max_ops: int,
-                 streams: int = 2):
+                 streams: int = 2, forks: Optional[int] = None):
         import torch
         from . import rsagpu
         self.torch = torch
         self.rsagpu = rsagpu
         self.ks = keyset
+        if forks is not None:
+            # streams a batch forks its widest CRT buckets onto, per executor
+            # stream (streams x (forks + 1) within the 4 hardware queues)
+            keyset.set_forks(forks)
+        self.forks = forks
         self.limbs = list(limbs_of_key)
         self.in_dev = torch.zeros(pool_words, dtype=torch.int32, device="cuda")
         self.out_dev = torch.zeros(pool_words, dtype=torch.int32, device="cuda")
