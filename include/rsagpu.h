@@ -108,6 +108,26 @@ int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *
                           uint32_t *out, size_t count, int limbs, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation and arguments as rsa_decrypt_crt_batch, with identical results,
+ * but the key-ordering scratch is the library's static device array (one
+ * copy per device, ~4.25 MiB, held until the process ends), so the call
+ * never allocates, whatever the stream or batch size.
+ * count <= RSA_CRT_STATIC_MAX_COUNT (RSA_EINVAL beyond, before any HIP call).
+ * Every call on a device shares that array: calls that overlap in time on
+ * one device (on different streams, or from different threads) race and
+ * may give wrong results; serialise them, for instance on one stream.
+ * Each call clears what it uses with a kernel (no memset), so it may be
+ * captured into a graph and replayed.  Returns RSA_EHIP if the array's
+ * device address cannot be looked up or a launch fails.
+ */
+#define RSA_CRT_STATIC_MAX_COUNT 1048576
+int rsa_decrypt_crt_batch_static(const uint32_t *c, const uint32_t *p, const uint32_t *q,
+                                 const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,
+                                 uint32_t *out, size_t count, int limbs, hipStream_t stream);
+
+/*
  * Execution plan used for a limb width: the limb radix the kernel computes
  * in (radix_bits = 32, or 29 for the reduced-radix kernels whose 64-bit
  * accumulators need no carry handling), the kernel's limb count in that
@@ -168,9 +188,10 @@ int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_op, int wind
 int rsa_autotune(int limbs, int kind, int exp_bits, size_t count, hipStream_t stream, rsa_plan *best);
 
 /*
- * Sets up the current device's library state (looks up the address of the
- * data-error counter, static device memory; allocates nothing).  Every
- * other entry point does this on first use.
+ * Sets up the current device's library state (looks up the addresses of
+ * the data-error counter and of rsa_decrypt_crt_batch_static's scratch,
+ * both static device memory; allocates nothing).  Every other entry point
+ * does this on first use.
  */
 int rsa_init(void);
 

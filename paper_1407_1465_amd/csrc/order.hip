@@ -121,6 +121,50 @@ std::vector<void *> g_outgrown;
 
 size_t key_order_bytes(size_t count) { return (count + kBuckets) * sizeof(unsigned); }
 
+// Scratch of the non-allocating CRT call: static device memory (one copy per
+// device, held until the process ends) for the bucket counters and the order
+// of up to kStaticOrderMax messages.  Host code never names the array in a
+// launch: its device address is looked up once per device (order_static_init)
+// and that address is what the kernels receive.  Every call on a device
+// shares the array, so such calls must not overlap in time on one device.
+static __device__ __align__(256) unsigned scratch[kBuckets + kStaticOrderMax];
+
+namespace {
+const int kMaxDev = 64;
+unsigned *g_static_order[kMaxDev];
+std::mutex g_static_mu;
+}  // namespace
+
+int order_static_init(int dev)
+{
+    if (dev < 0 || dev >= kMaxDev) return -1;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_order[dev]) return 0;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    g_static_order[dev] = static_cast<unsigned *>(ptr);
+    return 0;
+}
+
+unsigned *key_order_static(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
+                           hipStream_t stream)
+{
+    int dev = 0;
+    if (count > kStaticOrderMax || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+    unsigned *cnt = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        cnt = g_static_order[dev];
+    }
+    if (!cnt) return nullptr;
+    unsigned *order = cnt + kBuckets;
+    if (launch_order(p, dp, dq, count, hl, cnt, order, stream) != hipSuccess) return nullptr;
+    return order;
+}
+
 unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
                     hipStream_t stream)
 {

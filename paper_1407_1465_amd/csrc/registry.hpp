@@ -47,6 +47,16 @@ size_t key_order_bytes(size_t count);
 unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
                     hipStream_t stream);
 
+// The same order in the library's static device scratch (no allocation):
+// order_static_init looks up the scratch's address on device `dev` (once per
+// device, 0 on success); key_order_static then returns the order of up to
+// kStaticOrderMax messages, or nullptr (not set up, too many messages, or a
+// launch failure).  Calls on one device share the scratch.
+static const size_t kStaticOrderMax = (size_t)1 << 20;
+int order_static_init(int dev);
+unsigned *key_order_static(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
+                           hipStream_t stream);
+
 // Per-device data-error counter: two words of static device memory (the
 // count, and the value rsa_device_errors last took), looked up once per device.
 int device_state(unsigned long long **errs);

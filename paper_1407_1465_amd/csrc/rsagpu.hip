@@ -166,6 +166,8 @@ int device_state(unsigned long long **errs)
     if (!g_errs[dev]) {
         void *p = nullptr;
         if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_words)) != hipSuccess || !p) return RSA_EHIP;
+        // the non-allocating CRT call's static scratch on this device
+        if (order_static_init(dev) != 0) return RSA_EHIP;
         g_errs[dev] = static_cast<unsigned long long *>(p);
     }
     *errs = g_errs[dev];
@@ -223,6 +225,27 @@ extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const
     if (st != RSA_OK) return st;
     // more than one workgroup: process the messages grouped by key
     const unsigned *order = count > ng ? key_order(p, dp, dq, count, limbs / 2, stream) : nullptr;
+    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, count, limbs / 2, r.w, errs, stream));
+}
+
+static_assert(kStaticOrderMax == RSA_CRT_STATIC_MAX_COUNT, "static scratch size and its public limit agree");
+
+extern "C" int rsa_decrypt_crt_batch_static(const uint32_t *c, const uint32_t *p, const uint32_t *q,
+                                            const uint32_t *dp, const uint32_t *dq, const uint32_t *qinv,
+                                            uint32_t *out, size_t count, int limbs, hipStream_t stream)
+{
+    if (limbs < 2 || limbs > RSA_MAX_LIMBS || (limbs & 1)) return RSA_ELIMBS;
+    if (count == 0) return RSA_OK;
+    if (!c || !p || !q || !dp || !dq || !qinv || !out) return RSA_EINVAL;
+    if (count > RSA_CRT_STATIC_MAX_COUNT) return RSA_EINVAL;
+    Resolved r;
+    if (!resolve(limbs / 2, 1, &r)) return RSA_ELIMBS;
+    const size_t ng = 64 / r.inst->G;
+    unsigned long long *errs = nullptr;
+    const int st = device_state(&errs);
+    if (st != RSA_OK) return st;
+    const unsigned *order = nullptr;
+    if (count > ng && !(order = key_order_static(p, dp, dq, count, limbs / 2, stream))) return RSA_EHIP;
     return status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, count, limbs / 2, r.w, errs, stream));
 }
 

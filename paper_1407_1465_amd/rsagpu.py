@@ -28,6 +28,8 @@ _lib.rsa_modexp_batch.argtypes = [_P, _P, _P, _P, ctypes.c_size_t, ctypes.c_int,
 _lib.rsa_modexp_batch.restype = ctypes.c_int
 _lib.rsa_decrypt_crt_batch.argtypes = [_P] * 7 + [ctypes.c_size_t, ctypes.c_int, _P]
 _lib.rsa_decrypt_crt_batch.restype = ctypes.c_int
+_lib.rsa_decrypt_crt_batch_static.argtypes = [_P] * 7 + [ctypes.c_size_t, ctypes.c_int, _P]
+_lib.rsa_decrypt_crt_batch_static.restype = ctypes.c_int
 _lib.rsa_device_errors.argtypes = [_P, ctypes.POINTER(ctypes.c_uint64)]
 _lib.rsa_device_errors.restype = ctypes.c_int
 _lib.rsa_status_str.argtypes = [ctypes.c_int]
@@ -67,7 +69,7 @@ _lib.rsa_keyset_set_forks.argtypes = [_P, ctypes.c_int]
 _lib.rsa_keyset_set_forks.restype = ctypes.c_int
 
 # exported symbols, in the order include/rsagpu.h declares them
-EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_get_plan", "rsa_set_plan", "rsa_autotune", "rsa_init",
+EXPORTS = ("rsa_modexp_batch", "rsa_decrypt_crt_batch", "rsa_decrypt_crt_batch_static", "rsa_get_plan", "rsa_set_plan", "rsa_autotune", "rsa_init",
            "rsa_keyset_create", "rsa_keyset_add", "rsa_keyset_destroy", "rsa_ops_workspace_size",
            "rsa_ops_batch", "rsa_keyset_set_forks", "rsa_device_errors", "rsa_status_str", "rsa_version")
 
@@ -170,6 +172,30 @@ def decrypt_crt(c: torch.Tensor, p: torch.Tensor, q: torch.Tensor, dp: torch.Ten
     _check(_lib.rsa_decrypt_crt_batch(c.data_ptr(), p.data_ptr(), q.data_ptr(), dp.data_ptr(),
                                       dq.data_ptr(), qinv.data_ptr(), out.data_ptr(), count, limbs,
                                       _stream_handle(stream)), "rsa_decrypt_crt_batch")
+    return out
+
+
+CRT_STATIC_MAX_COUNT = 1 << 20
+
+
+def decrypt_crt_static(c: torch.Tensor, p: torch.Tensor, q: torch.Tensor, dp: torch.Tensor,
+                       dq: torch.Tensor, qinv: torch.Tensor, out: torch.Tensor,
+                       stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """decrypt_crt into a caller-provided `out` through the entry point that
+    never allocates device memory (rsa_decrypt_crt_batch_static: its scratch
+    is the library's static device array, shared by every call on a device,
+    so calls must not overlap in time; count <= CRT_STATIC_MAX_COUNT)."""
+    _operand(c, "c")
+    if c.dim() != 2:
+        raise ValueError("c must be (count, limbs)")
+    count, limbs = c.shape
+    hshape = (count, limbs // 2)
+    for name, t in (("p", p), ("q", q), ("dp", dp), ("dq", dq), ("qinv", qinv)):
+        _operand(t, name, hshape)
+    _operand(out, "out", c.shape)
+    _check(_lib.rsa_decrypt_crt_batch_static(c.data_ptr(), p.data_ptr(), q.data_ptr(), dp.data_ptr(),
+                                             dq.data_ptr(), qinv.data_ptr(), out.data_ptr(), count, limbs,
+                                             _stream_handle(stream)), "rsa_decrypt_crt_batch_static")
     return out
 
 

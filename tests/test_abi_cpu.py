@@ -51,6 +51,12 @@ def test_host_side_validation(lib):
     assert g(*([dummy] * 7), 4, 63, None) == -2                     # odd width
     assert g(*([dummy] * 6), None, 4, 64, None) == -1
     assert g(*([None] * 7), 0, 64, None) == 0
+    h = lib.rsa_decrypt_crt_batch_static
+    h.argtypes = [P] * 7 + [ctypes.c_size_t, ctypes.c_int, P]
+    assert h(*([dummy] * 7), 4, 63, None) == -2                     # odd width
+    assert h(*([dummy] * 6), None, 4, 64, None) == -1
+    assert h(*([None] * 7), 0, 64, None) == 0
+    assert h(*([dummy] * 7), (1 << 20) + 1, 64, None) == -1         # beyond the static scratch
     s = lib.rsa_status_str
     s.restype = ctypes.c_char_p
     assert s(0) == b"ok" and s(-2) == b"limb width out of range"
