@@ -47,6 +47,12 @@ import os
 import sys
 import time
 
+# Hardware queues per process: a mixed batch runs its widest CRT buckets on
+# up to three streams forked from the caller's, and the server keeps two
+# batches in flight, each with its forks; streams beyond the queues share
+# them and serialise (HIP's default is 4).  Set before the runtime starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -317,7 +323,7 @@ def cpu_baseline(oracle, base, exp, mod, gpu_out, unit, what, count=None, prefix
             "one_thread": {"value": k / wall1, "unit": unit, "sample": "first %d elements" % k}}
 
 
-def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0, streams=2, forks=1):
+def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0, streams=2, forks=3):
     """Serving run (256 x 2048-bit + 64 x 4096-bit resident keys, 70% CRT
     decryptions, 1..256 messages per request): the saturated request rate as
     the median of three closed bursts of 400 requests (after one unmeasured
@@ -381,6 +387,7 @@ def serve_leg(torch, np, rsagpu, W, seconds, plain_requests=0, streams=2, forks=
            "rate_req_per_s": rate, "saturated_req_per_s": sat["requests_per_s"],
            "saturation_bursts_req_per_s": [b["requests_per_s"] for b in bursts], "span_s": st["span_s"],
            "streams": len(ex.streams), "forks": forks, "max_inflight": ex.max_inflight,
+           "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
            "check": {"mismatches": bad + st["errors"] + errs,
                      "of": "all %d served messages through the opposite operation, plus failed requests "
                            "and device data errors" % nmsg},
@@ -432,9 +439,12 @@ def main():
                     help="length of the Poisson serving run (serve: 8 s; the default workload adds a 3 s run "
                          "for its request latencies, 0 leaves it out)")
     ap.add_argument("--no-tune", action="store_true", help="mixed: keep the default plans (no autotuning)")
+    ap.add_argument("--plan", action="append", default=[], metavar="WIDTH:KIND:RADIX:LANES:WINDOW",
+                    help="set a plan before running (rsa_set_plan; repeatable)")
     ap.add_argument("--serve-streams", type=int, default=2, help="serving: executor streams (batches in flight)")
-    ap.add_argument("--serve-forks", type=int, default=1,
-                    help="serving: streams each batch forks its widest CRT buckets onto")
+    ap.add_argument("--serve-forks", type=int, default=None,
+                    help="serving: streams each batch forks its widest CRT buckets onto (default: 3 with at "
+                         "least 8 hardware queues, else 1)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a known-size reference "
                          "dispatch for hardware traffic counters)")
@@ -452,6 +462,13 @@ def main():
     from paper_1407_1465_amd import rsagpu
     from paper_1407_1465_amd import workloads as W
     torch.cuda.set_device(0)
+    for spec in args.plan:
+        width, kind, radix, lanes, window = (int(v) for v in spec.split(":"))
+        rsagpu.set_plan(width, kind, radix, lanes, window)
+    if args.plan:
+        line_plans = args.plan
+    else:
+        line_plans = None
     if args.copy_mib:
         src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
         dst = torch.empty_like(src)
@@ -467,6 +484,8 @@ def main():
 
     if args.serve_seconds is None:
         args.serve_seconds = 8.0 if args.workload == "serve" else 3.0
+    if args.serve_forks is None:
+        args.serve_forks = 3 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) >= 8 else 1
     line = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "u32",
             "data": "synthetic (seeded keys and messages)"}
@@ -601,28 +620,28 @@ def main():
         ks = rsagpu.KeySet(len(wl.keys))
         for k in wl.keys:
             ks.add(k.limbs, k.n, k.e, k.p, k.q, k.dp, k.dq, k.qinv)
-        tuned = {}
-        if not args.no_tune:
-            # autotuned plans per size: the ops-batch plans (kind 2 encryption,
-            # kind 3 CRT half, kind 4 the CRT half of the widest class of a
-            # bulk batch), each timed on synthetic keys at this workload's
-            # bucket size
-            from paper_1407_1465_amd import tune
-            sizes = sorted({k.limbs for k in wl.keys})
-            for L in sizes:
-                nk = int(((wl.kinds == 0) & (np.array([wl.keys[i].limbs for i in wl.key_ids]) == L)).sum())
-                nd = int(((wl.kinds == 1) & (np.array([wl.keys[i].limbs for i in wl.key_ids]) == L)).sum())
-                kinds = [(2, nk), (4 if L == sizes[-1] else 3, nd)]
-                for kind, cnt in kinds:
-                    pl = tune.tune(L, kind, 0, cnt)
-                    tuned["%d-bit kind %d" % (32 * L, kind)] = {"radix_bits": pl.radix_bits,
-                                                                "lanes_per_op": pl.lanes_per_op,
-                                                                "window_bits": pl.window_bits}
-            print("# tuned plans: %s" % json.dumps(tuned), file=sys.stderr, flush=True)
         ops = rsagpu.pack_ops(wl.kinds, wl.key_ids, wl.in_offs, wl.in_offs).cuda()
         inp = dev(wl.in_pool)
         out = torch.zeros(wl.out_words, dtype=torch.int32, device="cuda")
         ws = torch.empty(rsagpu.ops_workspace_size(nops), dtype=torch.uint8, device="cuda")
+        tuned = {}
+        if not args.no_tune:
+            # autotuned plans per size for this batch: the ops-batch plans
+            # (kind 2 encryption, kind 3 CRT half, kind 4 the CRT half of the
+            # widest class of a bulk batch) tuned jointly on the call itself
+            from paper_1407_1465_amd import tune
+            widths = sorted({k.limbs for k in wl.keys}, reverse=True)
+            slots = [(L // 2, 4 if L == widths[0] else 3) for L in widths] + [(L, 2) for L in widths]
+            t_tune = time.perf_counter()
+            chosen, tuned_ms = tune.tune_batch(lambda: rsagpu.ops_batch(ks, ops, inp, out, ws), slots,
+                                               knobs=[("forks", [3, 2, 1, 0], ks.set_forks)])
+            names = {2: "encrypt", 3: "CRT half", 4: "CRT half (widest class of a bulk batch)"}
+            tuned = {"%d-bit %s" % (32 * key[0] if key[1] == 2 else 64 * key[0], names[key[1]]):
+                     {"radix_bits": p[0], "lanes_per_op": p[1], "window_bits": p[2]}
+                     for key, p in chosen.items() if isinstance(key, tuple)}
+            tuned["forks"] = chosen["forks"]
+            print("# tuned plans (%.1f s, %.2f ms per call): %s" % (time.perf_counter() - t_tune, tuned_ms,
+                                                                     json.dumps(tuned)), file=sys.stderr, flush=True)
         ms_eager, _ = timed(lambda: rsagpu.ops_batch(ks, ops, inp, out, ws), args.steps, args.warmup, torch)
         # the same call captured once into a HIP graph and replayed
         g = torch.cuda.CUDAGraph()
@@ -649,10 +668,14 @@ def main():
         if bad_words or errs:
             raise SystemExit("mixed batch round trip failed")
 
+        widest = max(k.limbs for k in wl.keys)
+
         def op_products(kk):
             kind, kid = kk
             k = wl.keys[kid]
-            pl = rsagpu.get_plan(k.limbs // 2 if kind else k.limbs, kind + 2)      # ops-batch plans
+            # the ops-batch plans: kind 4 for the widest class's CRT halves (a bulk batch)
+            pkind = (4 if k.limbs == widest else 3) if kind else 2
+            pl = rsagpu.get_plan(k.limbs // 2 if kind else k.limbs, pkind)
             return crt_products(k, pl) if kind else modexp_products(k, k.e, pl)
 
         def op_units(kk):
@@ -689,7 +712,10 @@ def main():
         ms_plain, _ = timed(plain, max(1, args.steps // 4), 1, torch)
         line.update(metric="mixed-size RSA ops/sec (1024-4096-bit, half CRT decrypt) on 1 GPU", unit="ops/s",
                     config={"workload": wl.name, "ops": nops, "keys": len(wl.keys),
-                            "plans": tuned or "default", "timed": "graph replay of one rsa_ops_batch call"})
+                            "plans": tuned or "default",
+                            "tuning": "coordinate descent over the plans per size and kind, timing the whole call"
+                            if tuned else None,
+                            "timed": "graph replay of one rsa_ops_batch call"})
         line["eager_ms_per_step"] = ms_eager
         line["batch_ms"] = {"p50": percentile(steps_ms, 50), "p99": percentile(steps_ms, 99)}
         line["plain_one_key_per_launch"] = {"value": nops / (ms_plain / 1e3), "ms_per_step": ms_plain,
@@ -830,6 +856,8 @@ def main():
         value = sv["requests_per_s"]
         ms, wall = sv["span_s"] * 1e3, sv["span_s"]
 
+    if line_plans:
+        line["config"]["plans_set"] = line_plans
     line["value"] = value
     line["ms_per_step"] = ms
     line["config"]["wall_s"] = wall

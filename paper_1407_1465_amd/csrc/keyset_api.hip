@@ -128,6 +128,7 @@ struct rsa_keyset {
     static const int kForkSets = 8;
     struct ForkSet {
         hipStream_t caller;
+        int made;                       // streams (and their events) created so far
         hipStream_t streams[kStreams];
         hipEvent_t fork;
         hipEvent_t done[kStreams];
@@ -227,9 +228,11 @@ extern "C" int rsa_keyset_destroy(rsa_keyset *ks)
     if (ks->stage_outs) (void)hipFree(ks->stage_outs);
     for (int i = 0; i < ks->nforksets; ++i) {
         rsa_keyset::ForkSet &f = ks->forksets[i];
-        for (hipStream_t s : f.streams) (void)hipStreamDestroy(s);
+        for (int t = 0; t < f.made; ++t) {
+            (void)hipStreamDestroy(f.streams[t]);
+            (void)hipEventDestroy(f.done[t]);
+        }
         (void)hipEventDestroy(f.fork);
-        for (hipEvent_t e : f.done) (void)hipEventDestroy(e);
     }
     delete[] ks->info;
     delete ks;
@@ -372,26 +375,30 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
     if (nfork > 0) {
         for (int i = 0; i < ks->nforksets; ++i)
             if (ks->forksets[i].caller == stream) fs = &ks->forksets[i];
-        if (!fs && ks->nforksets < rsa_keyset::kForkSets) {
-            // streams and events are made once per caller stream (never while
-            // the caller is being captured into a graph: no fork then)
-            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-            if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
-                rsa_keyset::ForkSet f{};
-                f.caller = stream;
-                int made = 0;
-                bool ok = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) == hipSuccess;
-                for (; ok && made < rsa_keyset::kStreams; ++made)
-                    ok = hipStreamCreateWithFlags(&f.streams[made], hipStreamNonBlocking) == hipSuccess &&
-                         hipEventCreateWithFlags(&f.done[made], hipEventDisableTiming) == hipSuccess;
-                if (!ok) return RSA_EHIP;
-                ks->forksets[ks->nforksets] = f;
-                fs = &ks->forksets[ks->nforksets++];
-            } else {
-                (void)hipGetLastError();
+        // streams and events are made once per caller stream, as many as the
+        // forks asked for so far (never while the caller is being captured
+        // into a graph: the call forks onto what exists)
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const bool capturing = hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+        (void)hipGetLastError();
+        if (!fs && !capturing && ks->nforksets < rsa_keyset::kForkSets) {
+            rsa_keyset::ForkSet &f = ks->forksets[ks->nforksets];
+            f = rsa_keyset::ForkSet{};
+            f.caller = stream;
+            if (hipEventCreateWithFlags(&f.fork, hipEventDisableTiming) != hipSuccess) return RSA_EHIP;
+            fs = &ks->forksets[ks->nforksets++];
+        }
+        if (fs && !capturing) {
+            for (; fs->made < nfork; ++fs->made) {
+                if (hipStreamCreateWithFlags(&fs->streams[fs->made], hipStreamNonBlocking) != hipSuccess)
+                    return RSA_EHIP;
+                if (hipEventCreateWithFlags(&fs->done[fs->made], hipEventDisableTiming) != hipSuccess) {
+                    (void)hipStreamDestroy(fs->streams[fs->made]);
+                    return RSA_EHIP;
+                }
             }
         }
-        if (!fs) nfork = 0;         // no fork set for this caller: every bucket on `stream`
+        nfork = fs ? (nfork < fs->made ? nfork : fs->made) : 0;    // no fork set: every bucket on `stream`
     }
     if (nfork > 0 && (e = hipEventRecord(fs->fork, stream)) != hipSuccess) return status_of(e);
     // Bucket order and streams: the CRT buckets of the widest classes are the
@@ -399,7 +406,10 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
     // waves cannot shorten), so each of them gets a keyset stream of its own;
     // the remaining buckets (narrower CRT classes, then all encryptions,
     // widest first) follow each other on the caller's stream, beside them,
-    // which then waits for the keyset streams.
+    // which then waits for the keyset streams.  The widest CRT bucket's
+    // waves also raise their issue priority: every call ends with its
+    // operations, whose chains are the longest, so on a SIMD shared with other
+    // buckets' waves they issue first.
     int order[kMaxBuckets], nb = 0;
     for (int kind = 1; kind >= 0; --kind)
         for (int cls = num_classes() - 1; cls >= 0; --cls)
@@ -420,7 +430,7 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         if (fork && (e = hipStreamWaitEvent(s, fs->fork, 0)) != hipSuccess) return status_of(e);
         const ops_launcher fn = kind == 0 ? r.inst->ops_enc : r.inst->ops_crt;
         e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b, counters + b,
-               in_pool, out_pool, r.w, blocks, pkind == 4 ? 1 : 0, s);
+               in_pool, out_pool, r.w, blocks, (kind == 1 && t == 0) ? 1 : 0, s);
         if (e != hipSuccess) return status_of(e);
         if (fork) {
             if ((e = hipEventRecord(fs->done[t], s)) != hipSuccess) return status_of(e);

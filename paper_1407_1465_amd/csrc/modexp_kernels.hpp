@@ -212,14 +212,16 @@ __device__ __forceinline__ void mont_sqr(uint32_t (&A)[S / G], uint32_t *abuf, c
 }
 
 // Montgomery constants of an odd modulus n > 1 in radix 2^B, R = 2^(B*S):
-//   one = R mod n:   2^(bitlen(n)-1) doubled B*S - bitlen(n) + 1 times;
-//   r2 = R^2 mod n:  X = R * 2^e mod n throughout, ending at e = B*S: R
-//                    doubled e0 times, e0 the top five bits of B*S, then
+//   one = R mod n:   2^(bitlen(n)-1) moved up B*S - bitlen(n) + 1 bits;
+//   r2 = R^2 mod n:  X = R * 2^e mod n throughout, ending at e = B*S: one
+//                    moved up e0 bits, e0 the top bits of B*S, then
 //                    left-to-right over its remaining bits X <- X*X/R (e
-//                    doubles) and one more doubling where the bit is set
-//                    (e + 1).  A doubling costs a few instructions per limb,
-//                    a Montgomery squaring hundreds, so the first squarings
-//                    of the ladder (e = 1, 2, 4, ...) are doublings instead.
+//                    doubles) and one doubling where the bit is set (e + 1).
+// In radix 2^32 the moves up are modular doublings (a carry chain per bit);
+// in the reduced radix (n < 2^(B*S - 10)) they go up to B - 1 bits at a time
+// by rgrp_shl_mod (one multiply by a limb and three carry chains), so e0
+// takes the top eight bits of B*S (128 <= e0 < 256) and four squarings fewer
+// remain than with the top five.
 template <int S, int G, int B>
 __device__ __forceinline__ void mont_setup(uint32_t (&one)[S / G], uint32_t (&r2)[S / G],
                                            const uint32_t (&n)[S / G], uint32_t n0inv, bool valid,
@@ -237,26 +239,60 @@ __device__ __forceinline__ void mont_setup(uint32_t (&one)[S / G], uint32_t (&r2
         for (int k = 0; k < L; ++k)
             if (r * L + k == top / B) one[k] = 1u << (top % B);
     }
-    const uint32_t ndbl = valid ? (uint32_t)(B * S) - bl + 1 : 0u;
-    const uint32_t maxd = wave_max(ndbl);
-    for (uint32_t t = 0; t < maxd; ++t) {
-        uint32_t y[L];
-#pragma unroll
-        for (int k = 0; k < L; ++k) y[k] = one[k];
-        A::dbl_mod(y, n);
-        const bool act = t < ndbl;
-#pragma unroll
-        for (int k = 0; k < L; ++k) one[k] = act ? y[k] : one[k];
-    }
+    const uint32_t nup = valid ? (uint32_t)(B * S) - bl + 1 : 0u;      // bits to move one up
     constexpr int E = B * S;
     constexpr int TOP = 31 - __builtin_clz((unsigned)E);
-    constexpr int SH = TOP > 4 ? TOP - 4 : 0;          // E >> SH in [16, 32)
+    if constexpr (B < 32) {
+        const double rn = 1.0 / rgrp_scaled<S, G, B>(n, 0u, (int)bl);
+        uint32_t left = nup;
 #pragma unroll
-    for (int k = 0; k < L; ++k) r2[k] = one[k];
-    for (int t = 0; t < (E >> SH); ++t) A::dbl_mod(r2, n);
-    for (int bit = SH - 1; bit >= 0; --bit) {
-        mont_sqr<S, G, B>(r2, abuf, n, n0inv);
-        if ((E >> bit) & 1) A::dbl_mod(r2, n);
+        for (int step = 0; step < 2; ++step) {
+            const uint32_t c = left < B - 1 ? left : (uint32_t)(B - 1);
+            uint32_t y[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) y[k] = one[k];
+            rgrp_shl_mod<S, G, B>(y, c ? c : 1u, n, rn, (int)bl);
+#pragma unroll
+            for (int k = 0; k < L; ++k) one[k] = c ? y[k] : one[k];
+            left -= c;
+        }
+        const uint32_t maxd = wave_max(left);
+        for (uint32_t t = 0; t < maxd; ++t) {
+            uint32_t y[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) y[k] = one[k];
+            A::dbl_mod(y, n);
+            const bool act = t < left;
+#pragma unroll
+            for (int k = 0; k < L; ++k) one[k] = act ? y[k] : one[k];
+        }
+        constexpr int SH = TOP > 7 ? TOP - 7 : 0;      // E >> SH in [128, 256)
+#pragma unroll
+        for (int k = 0; k < L; ++k) r2[k] = one[k];
+        for (int t = E >> SH; t > 0; t -= B - 1) rgrp_shl_mod<S, G, B>(r2, t < B - 1 ? t : B - 1, n, rn, (int)bl);
+        for (int bit = SH - 1; bit >= 0; --bit) {
+            mont_sqr<S, G, B>(r2, abuf, n, n0inv);
+            if ((E >> bit) & 1) A::dbl_mod(r2, n);
+        }
+    } else {
+        const uint32_t maxd = wave_max(nup);
+        for (uint32_t t = 0; t < maxd; ++t) {
+            uint32_t y[L];
+#pragma unroll
+            for (int k = 0; k < L; ++k) y[k] = one[k];
+            A::dbl_mod(y, n);
+            const bool act = t < nup;
+#pragma unroll
+            for (int k = 0; k < L; ++k) one[k] = act ? y[k] : one[k];
+        }
+        constexpr int SH = TOP > 4 ? TOP - 4 : 0;      // E >> SH in [16, 32)
+#pragma unroll
+        for (int k = 0; k < L; ++k) r2[k] = one[k];
+        for (int t = 0; t < (E >> SH); ++t) A::dbl_mod(r2, n);
+        for (int bit = SH - 1; bit >= 0; --bit) {
+            mont_sqr<S, G, B>(r2, abuf, n, n0inv);
+            if ((E >> bit) & 1) A::dbl_mod(r2, n);
+        }
     }
 }
 

@@ -145,6 +145,31 @@ __device__ __forceinline__ uint32_t rgrp_bitlen(const uint32_t (&x)[S / G])
     return grp_max<G>(bl);
 }
 
+// Sum over the group of one double per lane.  Every lane receives a sum of
+// all G values, but the order, and so the rounding, may differ between lanes:
+// a caller that needs one value takes lane 0's.
+template <int G>
+__device__ __forceinline__ double grp_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, G);
+    return v;
+}
+
+// (x + top * 2^(B*S)) / 2^e in double precision, for e near the value's bit
+// length (the top word is the group's top lane's; limbs far below 2^e
+// underflow harmlessly).
+template <int S, int G, int B>
+__device__ __forceinline__ double rgrp_scaled(const uint32_t (&x)[S / G], uint32_t top, int e)
+{
+    constexpr int L = S / G;
+    const int r = grp_lane<G>();
+    double part = r == G - 1 ? ldexp((double)top, B * S - e) : 0.0;
+#pragma unroll
+    for (int j = L - 1; j >= 0; --j) part += ldexp((double)x[j], B * (r * L + j) - e);
+    return grp_sum_f64<G>(part);
+}
+
 // ---- accumulator normalisation -----------------------------------------
 
 // Full: canonical B-bit limbs in w, returns the group's overflow beyond S
@@ -217,6 +242,46 @@ __device__ __forceinline__ void racc_lazy(uint32_t (&w)[S / G], const uint64_t (
     w[0] = ((uint32_t)v[0] & M) + in2;
 #pragma unroll
     for (int j = 1; j < L; ++j) w[j] = ((uint32_t)v[j] & M) + h2[j - 1];
+}
+
+// x = x * 2^c mod n for canonical x < n, n < 2^(B*S - 10) and 1 <= c <= B - 1,
+// given rn = 2^bl / n in double precision (bl the bit length of n).  y =
+// x * 2^c is S limbs plus a top word (the bits beyond them, in the group's top
+// lane).  q = floor(y / n) - 2 .. floor(y / n) comes from the doubles y / 2^bl
+// and rn: their product is y / n within a relative 2^-45 and y / n < 2^c, so
+// it is off by less than one, and q is its floor lowered by one (never below
+// zero), taken from the group's lane 0 so that every lane subtracts the same
+// q * n.  Then y - q * n < 3n fits S limbs, so it is the S-limb difference
+// modulo 2^(B*S), and at most two subtractions of n make it canonical.  One
+// call replaces c modular doublings (one carry chain each) by one multiply by
+// a limb and three carry chains.
+template <int S, int G, int B>
+__device__ __forceinline__ void rgrp_shl_mod(uint32_t (&x)[S / G], uint32_t c, const uint32_t (&n)[S / G], double rn,
+                                             int bl)
+{
+    constexpr int L = S / G;
+    constexpr uint32_t M = Radix<B>::MASK;
+    const uint32_t out = x[L - 1] >> (B - c);           // bits leaving this lane's top limb
+    const uint32_t in = grp_from_below<G>(out);
+    uint32_t y[L];
+#pragma unroll
+    for (int j = L - 1; j > 0; --j) y[j] = ((x[j] << c) & M) | (x[j - 1] >> (B - c));
+    y[0] = ((x[0] << c) & M) | in;
+    const uint32_t top = grp_lane<G>() == G - 1 ? out : 0u;
+    double qd = floor(rgrp_scaled<S, G, B>(y, top, bl) * rn) - 1.0;
+    qd = qd > 0.0 ? qd : 0.0;
+    const uint32_t q = grp_bcast0<G>((uint32_t)qd);
+    // q * n from 32-bit halves: a 64-bit product of the zero-extended limbs
+    // here would let the compiler share the extension of n with the
+    // exponentiation's products and lower those less well
+    uint64_t acc[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) acc[j] = ((uint64_t)__umulhi(q, n[j]) << 32) | (uint32_t)(q * n[j]);
+    uint32_t z[L];
+    (void)racc_normalise<S, G, B>(z, acc);              // q * n modulo 2^(B*S)
+    (void)rgrp_sub<S, G, B>(x, y, z);                   // y - q * n, exact below 2^(B*S)
+    rgrp_cond_sub<S, G, B>(x, 0u, n);
+    rgrp_cond_sub<S, G, B>(x, 0u, n);
 }
 
 // ---- Montgomery product, radix 2^B -----------------------------------------

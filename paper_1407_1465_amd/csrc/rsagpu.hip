@@ -67,11 +67,11 @@ struct Plan {
 // narrower group (more waves per operation) and a smaller LDS footprint (room
 // for the other buckets' waves) pay off.  Kind 4 is the CRT half of the
 // widest class of a bulk ops batch (rsa_ops_batch with at least
-// kBulkOps operations), whose end waits for that bucket's last operations:
-// for 4096-bit keys 16 lanes (S = 80) shorten one operation (a mixed batch
-// of 32768 takes 11% less time) but cost 64% more instructions per
-// operation, which a loaded server's smaller batches pay in latency (p50
-// +18%), so kind 3 keeps 8.
+// kBulkOps operations), whose end waits for that bucket's last operations.
+// For 4096-bit keys both take 16 lanes (S = 80): one operation's chain is
+// ~1.6x shorter than on 8 lanes for ~1.2x the lane-instructions, and a
+// serving batch, like a bulk one, ends with its 4096-bit decryptions (p99
+// 50 -> 34 ms against 8 lanes at the same request rate).
 static const int kKinds = 5;
 static const Plan kDefault[kKinds][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
@@ -82,7 +82,7 @@ static const Plan kDefault[kKinds][kNumClasses] = {
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 4, 3}, {29, 8, 4},
      {29, 4, 4}, {29, 8, 4}, {29, 16, 3}},
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
-     {29, 8, 5}, {29, 16, 4}, {29, 16, 3}},
+     {29, 16, 4}, {29, 16, 4}, {29, 16, 3}},
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
      {29, 16, 4}, {29, 16, 4}, {29, 16, 3}},
 };

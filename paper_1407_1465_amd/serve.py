@@ -12,8 +12,9 @@ resident (a keyset), and runs a scheduler tick loop:
      does not fit blocks the ones behind it, so admission is FIFO-fair);
   3. while fewer than `max_inflight` batches are on the GPU, pack every
      admitted request into one batch of operation descriptors and launch it
-     on the next stream (host-to-device copy of inputs and descriptors, one
-     rsa_ops_batch call, device-to-host copy of outputs, an event).
+     on an idle stream (one host-to-device copy of the descriptors and one of
+     the packed inputs, one rsa_ops_batch call, one device-to-host copy of
+     the outputs, an event).
 
 Requests that arrive while others are on the GPU are admitted as slots free
 up and launched in the next batch, so their work overlaps the running batch
@@ -218,11 +219,13 @@ class Server:
 
 class GpuExecutor:
     """Runs batches through rsa_ops_batch, each on an idle stream of its own
-    (at most one batch per stream, so max_inflight = streams).
+    (at most one uncollected batch per stream, so max_inflight = streams).
 
-    Inputs and outputs pass through pinned host mirrors of the device pools
-    (a request's slot range is the same in both), so a batch costs one
-    descriptor upload, one copy per request each way and one library call."""
+    A batch's inputs are packed back to back into the stream's pinned host
+    staging buffer and go to the device in one copy; its outputs come back
+    in one copy into the stream's pinned output buffer, from which collect()
+    slices each request.  The server's slot pools bound the words in flight
+    (memory-based admission); every stream's staging holds a full pool."""
 
     def __init__(self, keyset, limbs_of_key: Sequence[int], pool_words: int, max_ops: int,
                  streams: int = 2, forks: Optional[int] = None):
@@ -236,25 +239,27 @@ class GpuExecutor:
             # stream (streams x (forks + 1) within the 4 hardware queues)
             keyset.set_forks(forks)
         self.forks = forks
-        self.limbs = list(limbs_of_key)
-        self.in_dev = torch.zeros(pool_words, dtype=torch.int32, device="cuda")
-        self.out_dev = torch.zeros(pool_words, dtype=torch.int32, device="cuda")
-        self.in_host = torch.zeros(pool_words, dtype=torch.int32, pin_memory=True)
-        self.out_host = torch.zeros(pool_words, dtype=torch.int32, pin_memory=True)
-        self.in_np = self.in_host.numpy().view(np.uint32)
-        self.out_np = self.out_host.numpy().view(np.uint32)
+        self.limbs = np.asarray(list(limbs_of_key), dtype=np.int64)
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.in_dev = [torch.zeros(pool_words, dtype=torch.int32, device="cuda") for _ in range(streams)]
+        self.out_dev = [torch.zeros(pool_words, dtype=torch.int32, device="cuda") for _ in range(streams)]
+        self.in_host = [torch.zeros(pool_words, dtype=torch.int32, pin_memory=True) for _ in range(streams)]
+        self.out_host = [torch.zeros(pool_words, dtype=torch.int32, pin_memory=True) for _ in range(streams)]
+        self.in_np = [t.numpy().view(np.uint32) for t in self.in_host]
+        self.out_np = [t.numpy().view(np.uint32) for t in self.out_host]
         wsb = rsagpu.ops_workspace_size(max_ops)
         self.ws = [torch.empty(wsb, dtype=torch.uint8, device="cuda") for _ in range(streams)]
         self.ops_host = [torch.zeros((max_ops, 3), dtype=torch.int64, pin_memory=True) for _ in range(streams)]
+        self.ops_np = [t.numpy() for t in self.ops_host]
         self.ops_dev = [torch.zeros((max_ops, 3), dtype=torch.int64, device="cuda") for _ in range(streams)]
+        self.pool_words = pool_words
         self.max_ops = max_ops
         self.max_inflight = streams
-        self.last = [None] * streams           # completion event of each stream's batch
+        self.busy = [False] * streams           # a launched batch not yet collected
 
     def _idle_stream(self) -> int:
-        for k, ev in enumerate(self.last):
-            if ev is None or ev.query():
+        for k, b in enumerate(self.busy):
+            if not b:
                 return k
         raise RuntimeError("every stream has a batch in flight (more batches than streams)")
 
@@ -262,41 +267,48 @@ class GpuExecutor:
         torch = self.torch
         k = self._idle_stream()
         s = self.streams[k]
-        kinds, kids, ins, outs = [], [], [], []
-        for r in reqs:
-            L = self.limbs[r.key_id]
-            n = len(r.inputs)
-            kinds.append(np.full(n, r.kind, dtype=np.int64))
-            kids.append(np.full(n, r.key_id, dtype=np.int64))
-            ins.append(r.in_off + L * np.arange(n, dtype=np.int64))
-            outs.append(r.out_off + L * np.arange(n, dtype=np.int64))
-            self.in_np[r.in_off:r.in_off + r.words] = r.inputs.reshape(-1)
-        ops = self.rsagpu.pack_ops(np.concatenate(kinds), np.concatenate(kids), np.concatenate(ins),
-                                   np.concatenate(outs))
-        nops = ops.shape[0]
-        self.ops_host[k][:nops].copy_(ops)
+        counts = np.fromiter((len(r.inputs) for r in reqs), dtype=np.int64, count=len(reqs))
+        kinds = np.fromiter((r.kind for r in reqs), dtype=np.int64, count=len(reqs))
+        kids = np.fromiter((r.key_id for r in reqs), dtype=np.int64, count=len(reqs))
+        nops = int(counts.sum())
+        if nops > self.max_ops:
+            raise ValueError("batch of %d operations exceeds max_ops" % nops)
+        op_words = np.repeat(self.limbs[kids], counts)
+        offs = np.zeros(nops, dtype=np.int64)
+        np.cumsum(op_words[:-1], out=offs[1:])
+        total = int(offs[-1] + op_words[-1]) if nops else 0
+        if total > self.pool_words:
+            raise ValueError("batch of %d words exceeds the staging buffers" % total)
+        ops = self.ops_np[k]
+        ops[:nops, 0] = np.repeat(kinds, counts) | (np.repeat(kids, counts) << 32)
+        ops[:nops, 1] = offs
+        ops[:nops, 2] = offs
+        if reqs:
+            np.concatenate([r.inputs.reshape(-1) for r in reqs], out=self.in_np[k][:total])
+        first = np.zeros(len(reqs), dtype=np.int64)
+        np.cumsum(counts[:-1], out=first[1:])
         with torch.cuda.stream(s):
             self.ops_dev[k][:nops].copy_(self.ops_host[k][:nops], non_blocking=True)
-            for r in reqs:
-                self.in_dev[r.in_off:r.in_off + r.words].copy_(self.in_host[r.in_off:r.in_off + r.words],
-                                                               non_blocking=True)
-            self.rsagpu.ops_batch(self.ks, self.ops_dev[k], self.in_dev, self.out_dev, self.ws[k], nops=nops,
+            self.in_dev[k][:total].copy_(self.in_host[k][:total], non_blocking=True)
+            self.rsagpu.ops_batch(self.ks, self.ops_dev[k], self.in_dev[k], self.out_dev[k], self.ws[k], nops=nops,
                                   stream=s)
-            for r in reqs:
-                self.out_host[r.out_off:r.out_off + r.words].copy_(self.out_dev[r.out_off:r.out_off + r.words],
-                                                                   non_blocking=True)
+            self.out_host[k][:total].copy_(self.out_dev[k][:total], non_blocking=True)
             ev = torch.cuda.Event()
             ev.record(s)
-        self.last[k] = ev
-        return (ev, reqs)
+        self.busy[k] = True
+        starts = offs[first] if nops else first
+        return (ev, reqs, k, starts)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def collect(self, handle):
-        ev, reqs = handle
+        ev, reqs, k, starts = handle
         ev.synchronize()
-        return {r.rid: self.out_np[r.out_off:r.out_off + r.words].reshape(r.inputs.shape).copy() for r in reqs}
+        out = self.out_np[k]
+        res = {r.rid: out[o:o + r.words].reshape(r.inputs.shape).copy() for r, o in zip(reqs, starts.tolist())}
+        self.busy[k] = False
+        return res
 
 
 def poisson_requests(rate: float, n: int, seed: int, key_limbs: Sequence[int], key_moduli: Sequence[int],

@@ -8,6 +8,13 @@ calls for kinds 0 and 1, rsa_ops_batch on a synthetic keyset for kinds 2 to
 cached plans with rsa_set_plan so later processes skip the search.  Entries
 are keyed by the GPU architecture, the operand width in words, the kind, the
 exponent length and the batch size rounded up to a power of two.
+
+`tune_batch(run, slots)` tunes the plans of a whole rsa_ops_batch call
+jointly: the buckets of a mixed batch run side by side and compete for the
+CUs (registers, LDS, issue slots), so the plan that is fastest for a bucket
+alone (often the one with the shortest chain) need not be the fastest in the
+mix.  It installs each candidate plan of one (width, kind) slot at a time
+and times the real call, keeping the fastest (coordinate descent).
 """
 from __future__ import annotations
 
@@ -90,3 +97,72 @@ def apply_cached(arch: Optional[str] = None) -> int:
         rsagpu.set_plan(width, kind, e["radix_bits"], e["lanes_per_op"], e["window_bits"])
         n += 1
     return n
+
+
+def candidate_plans(width: int, kind: int):
+    """(radix_bits, lanes_per_op, window_bits) the library accepts for the
+    width class of `width` and plan `kind` (the current plan is restored;
+    none where the class has no plan of that kind)."""
+    try:
+        cur = rsagpu.get_plan(width, kind)
+    except rsagpu.RSAError:
+        return []
+    out = []
+    for radix in (32, 29):
+        for lanes in (1, 2, 4, 8, 16):
+            for w in range(2, 7):
+                try:
+                    rsagpu.set_plan(width, kind, radix, lanes, w)
+                except rsagpu.RSAError:
+                    continue
+                out.append((radix, lanes, w))
+    rsagpu.set_plan(width, kind, cur.radix_bits, cur.lanes_per_op, cur.window_bits)
+    return out
+
+
+def tune_batch(run, slots, reps: int = 3, passes: int = 1, tolerance: float = 0.005, knobs=()):
+    """Coordinate descent over the plans of `slots` [(width, kind), ...] for
+    the batch that run() enqueues on torch's current stream: each candidate
+    is installed and the batch timed (one warm-up, then `reps` runs between
+    HIP events); a candidate replaces the slot's plan when it is faster by
+    more than `tolerance`.  `knobs` [(name, values, apply)] are further
+    settings tuned the same way after the plans (apply(value) installs one;
+    values[0] is the current one).  Returns ({(width, kind): (radix, lanes,
+    window), name: value, ...}, ms per call with the chosen settings)."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def time_it() -> float:
+        run()
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    best = time_it()
+    chosen = {}
+    for _ in range(passes):
+        for width, kind in slots:
+            p = rsagpu.get_plan(width, kind)
+            cur = (p.radix_bits, p.lanes_per_op, p.window_bits)
+            for cand in candidate_plans(width, kind):
+                if cand == cur:
+                    continue
+                rsagpu.set_plan(width, kind, *cand)
+                ms = time_it()
+                if ms < best * (1.0 - tolerance):
+                    best, cur = ms, cand
+            rsagpu.set_plan(width, kind, *cur)
+            chosen[(width, kind)] = cur
+        for name, values, apply in knobs:
+            cur = values[0]
+            for v in values[1:]:
+                apply(v)
+                ms = time_it()
+                if ms < best * (1.0 - tolerance):
+                    best, cur = ms, v
+            apply(cur)
+            chosen[name] = cur
+    return chosen, best

@@ -110,10 +110,17 @@ def test_ops_batch_plans_are_separate():
         rsagpu.set_plan(32, 3, 0, 0, 0)
         rsagpu.set_plan(64, 2, 0, 0, 0)
     # kind 4: the widest CRT bucket of a bulk ops batch; 4096-bit halves on
-    # 16 lanes there (S = 80), on 8 in other ops batches
-    p4, p3 = rsagpu.get_plan(64, 4), rsagpu.get_plan(64, 3)
+    # 16 lanes (S = 80) there and in other ops batches; the plain CRT call
+    # keeps 8
+    p4, p3, p1 = rsagpu.get_plan(64, 4), rsagpu.get_plan(64, 3), rsagpu.get_plan(64, 1)
     assert (p4.radix_bits, p4.padded_limbs, p4.lanes_per_op) == (29, 80, 16)
-    assert p3.lanes_per_op == 8
+    assert (p3.radix_bits, p3.padded_limbs, p3.lanes_per_op) == (29, 80, 16)
+    assert p1.lanes_per_op == 8
+    rsagpu.set_plan(64, 4, 29, 8, 4)
+    try:
+        assert rsagpu.get_plan(64, 3) == p3                    # kinds 3 and 4 are set apart
+    finally:
+        rsagpu.set_plan(64, 4, 0, 0, 0)
     for kind in (-1, 5):
         with pytest.raises(Exception):
             rsagpu.get_plan(32, kind)
@@ -169,3 +176,18 @@ def test_mulpeak_library_exports_and_validates():
     assert mulpeak.LANES == 256 and mulpeak.CHAINS == 16 and mulpeak.SEED_WORDS == 256
     for name, val in (("MULPEAK_LANES", 256), ("MULPEAK_CHAINS", 16), ("MULPEAK_SEED_WORDS", 256)):
         assert re.search(r"#define %s %d\b" % (name, val), text)
+
+
+def test_candidate_plans_are_compiled_instances():
+    """The batch tuner's candidates for a class are exactly the plans the
+    library accepts (host-only calls), and the current plan is restored."""
+    from paper_1407_1465_amd import rsagpu, tune
+    before = rsagpu.get_plan(32, 3)
+    cands = tune.candidate_plans(32, 3)
+    assert rsagpu.get_plan(32, 3) == before
+    assert (29, 2, 4) in cands and (32, 4, 3) in cands
+    assert all(r in (29, 32) and 64 % g == 0 and 2 <= w <= 6 for r, g, w in cands)
+    assert not any(r == 29 and g == 8 for r, g, _ in cands)      # no radix-2^29 8-lane 36-limb instance
+    # wide classes have no CRT plans at all
+    assert tune.candidate_plans(96, 3) == []
+    assert len(tune.candidate_plans(128, 2)) > 0
