@@ -145,8 +145,8 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
             load_raw<S, G>(r2, mc.r2, live);
         }
         mont_mul_reg<S, G, B>(xt, x, r2, lds, n, n0inv);
-        group_modexp<S, G, B>(A, xt, k.e, k.words, live, n, n0inv, one, lds, w);
-        from_mont<S, G, B>(A, lds, n, n0inv);
+        if (!group_modexp<S, G, B, true>(A, xt, k.e, k.words, live, n, n0inv, one, lds, w, x))
+            from_mont<S, G, B>(A, lds, n, n0inv);
         store_words<S, G, B>(out_pool + op.out_off, A, k.words, live, true, lds);
     }
 }
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys
             Ar::cond_sub(xt, ovf, n);
         }
         uint32_t A[L];
-        group_modexp<H, G, B>(A, xt, half ? k.dq : k.dp, hl, live, n, n0inv, one, lds, w);
+        group_modexp<H, G, B>(A, xt, half ? k.dq : k.dp, hl, live, n, n0inv, one, lds, w, xt);
         from_mont<H, G, B>(A, lds, n, n0inv);
 
         if (half) {

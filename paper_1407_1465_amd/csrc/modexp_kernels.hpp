@@ -58,6 +58,13 @@ struct Arith {
     {
         rmont_mul_regs<S, G, B, true>(r, a, b, n, n0inv);
     }
+    // The same product with a canonical result (below n, canonical limbs).
+    static __device__ __forceinline__ void mont_mul_regs(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                         const uint32_t (&b)[L], const uint32_t (&n)[L],
+                                                         uint32_t n0inv)
+    {
+        rmont_mul_regs<S, G, B, false>(r, a, b, n, n0inv);
+    }
     // Lazy squares, symmetric (one product per limb pair) where kSqr: with a
     // in registers (G = 2, 4 or 16) or also staged in the group's slot of abuf.
     static constexpr bool kSqr = rsqr_fits<B, L>();
@@ -127,6 +134,12 @@ struct Arith<S, G, 32> {
     static __device__ __forceinline__ void mont_mul_regs_lazy(uint32_t (&r)[L], const uint32_t (&a)[L],
                                                               const uint32_t (&b)[L], const uint32_t (&n)[L],
                                                               uint32_t n0inv)
+    {
+        rsagpu::mont_mul_regs<S, G>(r, a, b, n, n0inv);
+    }
+    static __device__ __forceinline__ void mont_mul_regs(uint32_t (&r)[L], const uint32_t (&a)[L],
+                                                         const uint32_t (&b)[L], const uint32_t (&n)[L],
+                                                         uint32_t n0inv)
     {
         rsagpu::mont_mul_regs<S, G>(r, a, b, n, n0inv);
     }
@@ -354,12 +367,18 @@ struct ExpBits {
 // with A staged in the operand buffer) and its table products read one entry
 // for all groups.  Every product is lazy (A and the
 // table stay below 2n in redundant limbs); the caller's from_mont makes the
-// result canonical.
-template <int S, int G, int B>
-__device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
+// result canonical.  With FUSE, x holds the base itself (not in Montgomery
+// form): where the wave's one schedule ends with a product by T[0] = x R
+// (an exponent whose last window is its lowest bit alone, such as 65537),
+// that last product takes x instead and is not lazy, A * x / R = x^e mod n,
+// canonical; group_modexp then returns true and the caller's from_mont is
+// left out (one Montgomery product less).  It returns false otherwise.
+template <int S, int G, int B, bool FUSE = false>
+__device__ __forceinline__ bool group_modexp(uint32_t (&A)[S / G], const uint32_t (&xt)[S / G],
                                                      const uint32_t *ep, int elimbs, bool use_exp,
                                                      const uint32_t (&n)[S / G], uint32_t n0inv,
-                                                     const uint32_t (&one)[S / G], uint32_t *lds, int w)
+                                                     const uint32_t (&one)[S / G], uint32_t *lds, int w,
+                                                     const uint32_t (&x)[S / G])
 {
     using Ly = Layout<S, G>;
     using Ar = Arith<S, G, B>;
@@ -474,7 +493,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
             pos = __builtin_amdgcn_readfirstlane((int)ebits) - 1;
 #pragma unroll
             for (int k = 0; k < L; ++k) A[k] = one[k];
-            if (pos < 0) return;
+            if (pos < 0) return false;
             eb.start(pos);
             next_window();                      // the leading window sets A
             lds_get<S, G>(A, tbl + __builtin_amdgcn_readfirstlane(mi) * Ly::WORDS, g);
@@ -491,6 +510,13 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
                         Ar::sqr_lds_lazy(A, A, abuf, n, n0inv);
                     }
                 }
+                if constexpr (FUSE) {
+                    if (ui == 0 && __builtin_amdgcn_readfirstlane(pos) < 0) {
+                        if constexpr (REG) Ar::mont_mul_regs(A, A, x, n, n0inv);
+                        else mont_mul_reg<S, G, B>(A, A, x, abuf, n, n0inv);
+                        return true;
+                    }
+                }
                 if (ui >= 0) {
                     if constexpr (REG) {
                         uint32_t tb[L];
@@ -501,7 +527,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
                     }
                 }
             }
-            return;
+            return false;
         }
     }
 
@@ -546,6 +572,7 @@ __device__ __forceinline__ void group_modexp(uint32_t (&A)[S / G], const uint32_
         else if (sq > 0) --sq;
         if (sq == 0 && mi < 0 && pos >= 0) next_window();
     }
+    return false;
 }
 
 // A = A * R^-1 mod n (leave Montgomery form).
@@ -589,8 +616,8 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_modexp(const uint3
     uint32_t one[L], r2[L], xt[L], A[L];
     mont_setup<S, G, B>(one, r2, n, n0inv, valid, lds);
     mont_mul_reg<S, G, B>(xt, x, r2, lds, n, n0inv);
-    group_modexp<S, G, B>(A, xt, exp + off, limbs, valid, n, n0inv, one, lds, w);
-    from_mont<S, G, B>(A, lds, n, n0inv);
+    if (!group_modexp<S, G, B, true>(A, xt, exp + off, limbs, valid, n, n0inv, one, lds, w, x))
+        from_mont<S, G, B>(A, lds, n, n0inv);
 
     store_words<S, G, B>(out + off, A, limbs, live, valid, lds);
     if (live && r == 0 && !valid && bl != 1) atomicAdd(errs, 1ull);
@@ -661,7 +688,7 @@ __global__ __launch_bounds__(128) void k_crt(const uint32_t *__restrict__ c, con
     }
 
     uint32_t A[L];
-    group_modexp<H, G, B>(A, xt, (half ? dq : dp) + hoff, hl, valid, n, n0inv, one, lds, w);
+    group_modexp<H, G, B>(A, xt, (half ? dq : dp) + hoff, hl, valid, n, n0inv, one, lds, w, xt);
     from_mont<H, G, B>(A, lds, n, n0inv);
 
     // wave 1 hands m_q and its validity to wave 0

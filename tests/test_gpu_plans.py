@@ -77,7 +77,11 @@ def test_instance_modexp_shared_exponent(B, S, G, plan_guard):
     """Waves whose groups all carry the same exponent words (one key's
     exponent, a public exponent) run one schedule for the whole wave with
     symmetric squarings; a wave with one differing exponent, and the ragged
-    last wave, must give the same results as the per-group schedule."""
+    last wave, must give the same results as the per-group schedule.  An
+    exponent whose last window is its lowest bit alone (65537, 17) ends with
+    one product by the base itself in place of the conversion out of the
+    Montgomery domain: bases of any size below 2^(32 limbs), also far above a
+    short modulus, must come out reduced."""
     cls = width_class(B, S)
     rsagpu.set_plan(cls, 0, B, G, window_for(B, S, G))
     plan_guard.append((cls, 0))
@@ -93,6 +97,10 @@ def test_instance_modexp_shared_exponent(B, S, G, plan_guard):
     cases = [(bases, exps, mods)]
     for e in (0, 1, 2, 3, 1 << (bits - 1), (1 << bits) - 1, 65537):
         cases.append((bases[:ng + 1], [e] * (ng + 1), mods[:ng + 1]))
+    short = [rng.getrandbits(bits // 2) | 1 | (1 << (bits // 2 - 1)) for _ in range(ng + 1)]
+    big = [(1 << bits) - 1 - rng.getrandbits(bits // 4) for _ in range(ng + 1)]
+    for e in (65537, 17):
+        cases.append((big, [e] * (ng + 1), short))
     for bs, es, ms in cases:
         Bv, Ev, Mv = (W.ints_to_limbs(v, limbs) for v in (bs, es, ms))
         out = host(rsagpu.modexp(dev(Bv), dev(Ev), dev(Mv)))
