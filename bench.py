@@ -50,8 +50,11 @@ import time
 # Hardware queues per process: a mixed batch runs its widest CRT buckets on
 # up to three streams forked from the caller's, and the server keeps two
 # batches in flight, each with its forks; streams beyond the queues share
-# them and serialise (HIP's default is 4).  Set before the runtime starts.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# them and serialise in submission order (HIP's default is 4, one of them
+# the null stream's).  Raised to 8 before the runtime starts, unless the
+# environment asks for more.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -710,6 +713,27 @@ def main():
                 else:
                     rsagpu.modexp(x, *a, out=o)
         ms_plain, _ = timed(plain, max(1, args.steps // 4), 1, torch)
+        # each (size, kind) bucket of the batch alone, with the same plans
+        # (a call that small takes kind 3 for its CRT bucket: for the widest
+        # one kind 3 holds kind 4's plan while it is timed)
+        alone = {}
+        limbs_of = np.array([wl.keys[i].limbs for i in wl.key_ids])
+        sizes = sorted(set(limbs_of.tolist()), reverse=True)
+        for L in sizes:
+            for kind in (1, 0):
+                idx = np.nonzero((limbs_of == L) & (wl.kinds == kind))[0]
+                if not idx.size:
+                    continue
+                swap = kind == 1 and L == sizes[0]
+                if swap:
+                    p3, p4 = rsagpu.get_plan(L // 2, 3), rsagpu.get_plan(L // 2, 4)
+                    rsagpu.set_plan(L // 2, 3, p4.radix_bits, p4.lanes_per_op, p4.window_bits)
+                sub = rsagpu.pack_ops(wl.kinds[idx], wl.key_ids[idx], wl.in_offs[idx], wl.in_offs[idx]).cuda()
+                ms_b, _ = timed(lambda: rsagpu.ops_batch(ks, sub, inp, out, ws, nops=len(idx)), 3, 1, torch)
+                if swap:
+                    rsagpu.set_plan(L // 2, 3, p3.radix_bits, p3.lanes_per_op, p3.window_bits)
+                alone["%d-bit %s" % (32 * L, "CRT" if kind else "encrypt")] = {"ops": int(idx.size), "ms": ms_b}
+        line["buckets_alone_ms"] = alone
         line.update(metric="mixed-size RSA ops/sec (1024-4096-bit, half CRT decrypt) on 1 GPU", unit="ops/s",
                     config={"workload": wl.name, "ops": nops, "keys": len(wl.keys),
                             "plans": tuned or "default",

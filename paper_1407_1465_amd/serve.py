@@ -236,7 +236,9 @@ class GpuExecutor:
         self.ks = keyset
         if forks is not None:
             # streams a batch forks its widest CRT buckets onto, per executor
-            # stream (streams x (forks + 1) within the 4 hardware queues)
+            # stream: streams x (forks + 1) streams, which overlap only while
+            # the runtime has a hardware queue for each (GPU_MAX_HW_QUEUES,
+            # 4 by default, one of them the null stream's)
             keyset.set_forks(forks)
         self.forks = forks
         self.limbs = np.asarray(list(limbs_of_key), dtype=np.int64)
