@@ -29,10 +29,13 @@ line carries
                 batch step time;
   check:        elements of the whole batch whose round trip through the
                 opposite operation (decryptions re-encrypted, encryptions
-                decrypted) differs; the run fails unless it is 0.
+                decrypted) differs; the run fails unless it is 0;
+  encrypt:      the same batch's messages encrypted with e = 65537, with its
+                own rate, roofline, check and oracle comparison.
 
-Other workloads (--workload): rsa64, rsa1024 (full-d decryption, no CRT),
-enc2048 (e = 65537 encryption of the default batch), mixed (32768 operations
+Other workloads (--workload): rsa64, rsa1024 (full-d decryption, no CRT, and
+under `encrypt` the same messages' e = 65537 encryptions), enc2048 (e = 65537
+encryption of the default batch), mixed (32768 operations
 over 1024..4096-bit keys in one rsa_ops_batch call), serve (Poisson requests
 through the continuous-batching server: p50/p99 latency and throughput),
 paper (the paper's own Section 10 experiment: one-word keys n = 131*137 and
@@ -485,6 +488,31 @@ def main():
     def tab(wl, attr, width):
         return np.ascontiguousarray(W.ints_to_limbs([getattr(k, attr) for k in wl.keys], width)[wl.key_of])
 
+    def encrypt_half(wl, L, n_h, e_h, decrypt):
+        """The batch's other half: every message encrypted (e = 65537) with
+        its key, timed like the line's own operation, each output decrypted
+        back (`decrypt`) against its message and, with the CPU baseline on,
+        compared with the oracle's."""
+        m, e, n = dev(wl.msgs), dev(e_h), dev(n_h)
+        out = torch.empty_like(m)
+        plan = rsagpu.get_plan(L, 0)
+        count = len(wl.msgs)
+        ms_e, _ = timed(lambda: rsagpu.modexp(m, e, n, out=out), args.steps, args.warmup, torch)
+        bad = row_mismatches(decrypt(out), m)
+        if bad:
+            raise SystemExit("encryption round trip failed on %d elements" % bad)
+        per_unit = unit_enc_products(L)
+        as_run = per_key_sum(wl.key_of, lambda k: modexp_products(wl.keys[k], wl.keys[k].e, plan))
+        sub = {"value": count / (ms_e / 1e3), "unit": "encryptions/s", "ms_per_step": ms_e,
+               "roofline": roofline(per_unit * count, ms_e, "k_modexp<%d,%d,%d>" % (
+                   plan.padded_limbs, plan.lanes_per_op, plan.radix_bits), per_unit, count, as_run),
+               "check": {"mismatches": bad, "of": "all %d encryptions, decrypted against the messages" % count}}
+        if args.cpu_sample:
+            import oracle
+            sub["cpu_baseline"] = cpu_baseline(oracle, wl.msgs, e_h, n_h, out.cpu().numpy().view(np.uint32),
+                                               "encryptions/s", "m^65537 mod n")
+        return sub
+
     if args.serve_seconds is None:
         args.serve_seconds = 8.0 if args.workload == "serve" else 3.0
     if args.serve_forks is None:
@@ -546,6 +574,8 @@ def main():
                 cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32), "decryptions/s",
                                    "plain C^d mod n (no CRT)",
                                    None if args.cpu_sample < 0 else min(args.cpu_sample, count))
+            line["encrypt"] = encrypt_half(wl, L, n_h, e_h,
+                                           lambda x: rsagpu.decrypt_crt(x, p, q, dp, dq, qi))
             if args.serve_seconds > 0:
                 sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds, streams=args.serve_streams,
                                forks=args.serve_forks)
@@ -615,6 +645,9 @@ def main():
             import oracle
             cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32), "decryptions/s",
                                "plain C^d mod n")
+        line["encrypt"] = encrypt_half(wl, L, n_h, tab(wl, "e", L), lambda x: rsagpu.modexp(x, d, n))
+        if L <= 2:
+            line["encrypt"]["roofline"]["note"] = "launch-bound: one launch of 19 dependent products"
         value = count / (ms / 1e3)
 
     elif args.workload == "mixed":
