@@ -134,8 +134,10 @@ int rsa_decrypt_crt_batch_static(const uint32_t *c, const uint32_t *p, const uin
  * radix (padded_limbs), lanes per exponentiation (G), limbs per lane
  * (padded_limbs / G), window width in exponent bits (a sliding window over
  * the 2^(window_bits-1) odd powers, paper Section 3.6.5) and the LDS bytes
- * per wave (the CRT kernels run workgroups of two waves, one per half, and
- * take twice that per workgroup).
+ * per wave.  The CRT kernels run a wave per half: rsa_decrypt_crt_batch in
+ * workgroups of one pair of waves, or of two pairs where lanes_per_op is 8
+ * or 16 (one wave per SIMD of a CU), rsa_ops_batch in workgroups of one
+ * pair, so a workgroup takes 2 or 4 times lds_bytes.
  * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
  * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
  * operations inside rsa_ops_batch (separate plans: its buckets are smaller
@@ -159,7 +161,9 @@ int rsa_get_plan(int limbs, int kind, rsa_plan *plan);
  * Overrides the plan of the width class that `limbs` maps to (kind as in
  * rsa_get_plan): (radix_bits, lanes_per_op) must name a compiled kernel
  * instance for that class, 2 <= window_bits <= 7, and the plan's LDS
- * (lds_bytes of rsa_get_plan) must fit 64 KiB.  All three zero restores the
+ * (lds_bytes of rsa_get_plan) must fit 64 KiB; for a CRT kind (1, 3, 4) the
+ * workgroup's LDS (2 or 4 times lds_bytes, as above, plus 16 bytes) must
+ * also fit the 160 KiB a workgroup may hold.  All three zero restores the
  * default.
  * Used by the tuner; affects calls issued afterwards from any thread.
  * Pure host call.

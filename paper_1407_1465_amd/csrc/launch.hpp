@@ -74,6 +74,30 @@ inline size_t lds_bytes_for(int S, int G, int B, int w)
     return (size_t)lds_entries(B, G, w) * (size_t)S * (size_t)(64 / G) * 4u;
 }
 
+// p/q wave pairs per workgroup of the plain CRT kernel (k_crt).  A CU that
+// receives a second two-wave workgroup while others have none has been
+// measured to run both on the same two SIMDs (a launch of 273 such
+// workgroups took 1.57x as long as one of 250), so where the waves hold few
+// messages (8 or 16 lanes per half: a batch of them is few workgroups, and
+// little LDS keeps several resident) a workgroup carries two pairs, one wave
+// per SIMD, and half as many workgroups cover a batch.  The ops-batch CRT
+// kernel keeps one pair: beside other buckets' waves, four-wave workgroups
+// wait longer for a CU with room on every SIMD (served requests' p99 latency
+// rose from 25 to 31-33 ms with them).
+__host__ __device__ constexpr int crt_pairs(int G) { return G >= 8 ? 2 : 1; }
+
+// LDS one workgroup may allocate on gfx950, and the CRT kernels' own LDS
+// beyond the waves' regions (the ops kernel's claim word, aligned).
+constexpr size_t kMaxGroupLds = 160 * 1024;
+constexpr size_t kCrtOwnLds = 16;
+
+// A CRT workgroup of `pairs` pairs of waves (each with its window table and
+// buffers) of this plan fits in LDS.
+inline bool crt_lds_fits(int S, int G, int B, int w, int pairs)
+{
+    return 2 * (size_t)pairs * lds_bytes_for(S, G, B, w) + kCrtOwnLds <= kMaxGroupLds;
+}
+
 template <int S, int G, int B>
 hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32_t *mod, uint32_t *out,
                          size_t count, int limbs, int w, unsigned long long *errs, hipStream_t stream);

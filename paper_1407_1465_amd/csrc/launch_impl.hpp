@@ -22,10 +22,12 @@ hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, c
                       const uint32_t *dq, const uint32_t *qinv, const unsigned *order, uint32_t *out, size_t count,
                       int hl, int w, unsigned long long *errs, hipStream_t stream)
 {
-    const size_t ng = 64 / G;                  // messages per two-wave workgroup
+    constexpr int P = crt_pairs(G);
+    if (!crt_lds_fits(H, G, B, w, P)) return hipErrorInvalidValue;
+    const size_t ng = (64 / G) * P;            // messages per workgroup (P pairs of waves)
     const size_t blocks = (count + ng - 1) / ng;
-    hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(128), 2 * lds_bytes_for(H, G, B, w), stream, c,
-                       p, q, dp, dq, qinv, order, out, (unsigned long long)count, hl, w, errs);
+    hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(128 * P), 2 * P * lds_bytes_for(H, G, B, w),
+                       stream, c, p, q, dp, dq, qinv, order, out, (unsigned long long)count, hl, w, errs);
     return hipGetLastError();
 }
 
@@ -55,6 +57,7 @@ hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned 
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                           int urgent, hipStream_t stream)
 {
+    if (!crt_lds_fits(S, G, B, w, 1)) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(128), 2 * lds_bytes_for(S, G, B, w), stream, keys,
                        ops, list, count, counter, in_pool, out_pool, w, urgent);
     return hipGetLastError();

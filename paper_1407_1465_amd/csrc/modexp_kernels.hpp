@@ -625,31 +625,33 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_modexp(const uint3
 
 // ---- CRT decryption ------------------------------------------------------
 //
-// A workgroup of two waves takes NG = 64 / G messages: wave 0 the halves
-// modulo p, wave 1 the halves modulo q, one message per lane group, so a
+// A pair of waves takes NG = 64 / G messages: the pair's wave 0 the halves
+// modulo p, its wave 1 the halves modulo q, one message per lane group, so a
 // wave's exponents are all dp (or all dq) and, when its messages share a key,
-// equal (group_modexp then runs one schedule with symmetric squarings).
-// Message i of the workgroup is order[blockIdx.x * NG + i] (the identity
-// without an order).  p, q, dp, dq, qinv have hl 32-bit words, c and the
-// result 2*hl; H limbs of radix 2^B hold a half (B*H >= 32*hl).  Each wave
-// works in its own LDS region; m_q and its validity reach wave 0 through
-// wave 1's region, and wave 0 recombines (Garner) and stores.
+// equal (group_modexp then runs one schedule with symmetric squarings).  A
+// workgroup holds P = crt_pairs(G) pairs, which take consecutive runs of NG
+// messages: message i of pair j is order[(blockIdx.x * P + j) * NG + i] (the
+// identity without an order).  p, q, dp, dq, qinv have hl 32-bit words, c
+// and the result 2*hl; H limbs of radix 2^B hold a half (B*H >= 32*hl).
+// Each wave works in its own LDS region; m_q and its validity reach the
+// pair's wave 0 through its wave 1's region, and wave 0 recombines (Garner)
+// and stores.
 template <int H, int G, int B>
-__global__ __launch_bounds__(128) void k_crt(const uint32_t *__restrict__ c, const uint32_t *__restrict__ p,
-                                             const uint32_t *__restrict__ q, const uint32_t *__restrict__ dp,
-                                             const uint32_t *__restrict__ dq, const uint32_t *__restrict__ qinv,
-                                             const unsigned *__restrict__ order, uint32_t *out,
-                                             unsigned long long count, int hl, int w, unsigned long long *errs)
+__global__ __launch_bounds__(128 * crt_pairs(G)) void k_crt(
+    const uint32_t *__restrict__ c, const uint32_t *__restrict__ p, const uint32_t *__restrict__ q,
+    const uint32_t *__restrict__ dp, const uint32_t *__restrict__ dq, const uint32_t *__restrict__ qinv,
+    const unsigned *__restrict__ order, uint32_t *out, unsigned long long count, int hl, int w,
+    unsigned long long *errs)
 {
     using Ar = Arith<H, G, B>;
     using Ly = Layout<H, G>;
-    constexpr int L = H / G, NG = 64 / G;
-    const int half = (int)(threadIdx.x >> 6);
+    constexpr int L = H / G, NG = 64 / G, P = crt_pairs(G);
+    const int wave = (int)(threadIdx.x >> 6), pair = wave >> 1, half = wave & 1;
     const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
-    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + half * region;
-    uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + region;     // wave 1's region
+    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + wave * region;
+    uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + (2 * pair + 1) * region;   // the pair's wave 1
     const int g = grp_index<G>(), r = grp_lane<G>();
-    const unsigned long long slot = (unsigned long long)blockIdx.x * NG + g;
+    const unsigned long long slot = ((unsigned long long)blockIdx.x * P + pair) * NG + g;
     const bool live = slot < count;
     const unsigned long long msg = live ? (order ? (unsigned long long)order[slot] : slot) : 0ull;
     const size_t hoff = live ? (size_t)msg * (size_t)hl : 0;

@@ -71,14 +71,17 @@ struct Plan {
 // For 4096-bit keys both take 16 lanes (S = 80): one operation's chain is
 // ~1.6x shorter than on 8 lanes for ~1.2x the lane-instructions, and a
 // serving batch, like a bulk one, ends with its 4096-bit decryptions (p99
-// 50 -> 34 ms against 8 lanes at the same request rate).
+// 50 -> 34 ms against 8 lanes at the same request rate).  The plain CRT call
+// takes 16 lanes and a 5-bit window for 4096-bit keys too: with two wave
+// pairs per workgroup, 256, 1092 and 4368 decryptions took 6.2, 7.1 and
+// 17.3 ms against 9.8, 10.9 and 20.4 ms on 8 lanes with a 4-bit window.
 static const int kKinds = 5;
 static const Plan kDefault[kKinds][kNumClasses] = {
     // classes:  2 .. 12 limbs in radix 2^32; 16 .. 128 limbs in radix 2^29
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 2, 3}, {29, 8, 4},
      {29, 4, 4}, {29, 16, 4}, {29, 16, 3}},
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 2, 4}, {29, 8, 4},
-     {29, 8, 4}, {29, 16, 4}, {29, 16, 3}},
+     {29, 16, 5}, {29, 16, 4}, {29, 16, 3}},
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {29, 2, 4}, {29, 4, 4}, {29, 4, 3}, {29, 8, 4},
      {29, 4, 4}, {29, 8, 4}, {29, 16, 3}},
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
@@ -279,6 +282,8 @@ extern "C" int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_o
     if (!in || (crt_kind(kind) && !(in->crt && in->ops_crt))) return RSA_EINVAL;
     if (window_bits < 2 || window_bits > 7) return RSA_EINVAL;
     if (lds_bytes_for(in->S, in->G, in->B, window_bits) > 64 * 1024) return RSA_EINVAL;
+    if (crt_kind(kind) && !crt_lds_fits(in->S, in->G, in->B, window_bits, kind == 1 ? crt_pairs(in->G) : 1))
+        return RSA_EINVAL;
     g_plan[kind][i].store(pack(Plan{radix_bits, lanes_per_op, window_bits}));
     return RSA_OK;
 }

@@ -110,12 +110,12 @@ def test_ops_batch_plans_are_separate():
         rsagpu.set_plan(32, 3, 0, 0, 0)
         rsagpu.set_plan(64, 2, 0, 0, 0)
     # kind 4: the widest CRT bucket of a bulk ops batch; 4096-bit halves on
-    # 16 lanes (S = 80) there and in other ops batches; the plain CRT call
-    # keeps 8
+    # 16 lanes (S = 80) there, in other ops batches and in the plain CRT call
+    # (there with a 5-bit window)
     p4, p3, p1 = rsagpu.get_plan(64, 4), rsagpu.get_plan(64, 3), rsagpu.get_plan(64, 1)
     assert (p4.radix_bits, p4.padded_limbs, p4.lanes_per_op) == (29, 80, 16)
     assert (p3.radix_bits, p3.padded_limbs, p3.lanes_per_op) == (29, 80, 16)
-    assert p1.lanes_per_op == 8
+    assert (p1.lanes_per_op, p1.window_bits) == (16, 5)
     rsagpu.set_plan(64, 4, 29, 8, 4)
     try:
         assert rsagpu.get_plan(64, 3) == p3                    # kinds 3 and 4 are set apart
@@ -126,6 +126,37 @@ def test_ops_batch_plans_are_separate():
             rsagpu.get_plan(32, kind)
         with pytest.raises(Exception):
             rsagpu.set_plan(32, kind, 29, 4, 3)
+
+
+def test_crt_plans_fit_the_workgroup_lds():
+    """The plain CRT call runs two pairs of waves per workgroup where a half
+    has 8 or 16 lanes: its window tables must fit 160 KiB four times over
+    (plus 16 bytes).  The ops-batch CRT kinds run one pair (twice over), and
+    plain exponentiation one wave."""
+    from paper_1407_1465_amd import rsagpu
+    try:
+        rsagpu.set_plan(64, 1, 29, 16, 5)                           # 2048-bit halves: 4 x 20480 bytes
+        with pytest.raises(Exception):
+            rsagpu.set_plan(64, 1, 29, 16, 6)                       # 4 x 40960 + 16 > 160 KiB
+        for kind in (3, 4):
+            rsagpu.set_plan(64, kind, 29, 16, 6)                    # 2 x 40960 + 16
+        rsagpu.set_plan(48, 1, 29, 8, 5)                            # 1536-bit halves: 4 x 28672
+        with pytest.raises(Exception):
+            rsagpu.set_plan(48, 1, 29, 8, 6)                        # 4 x 57344
+        rsagpu.set_plan(32, 1, 29, 2, 4)                            # one pair: 2 x 36864
+        rsagpu.set_plan(64, 0, 29, 16, 6)                           # one wave: 40960
+        assert rsagpu.get_plan(64, 0).lds_bytes == 40960
+        for limbs, kind in ((64, 1), (64, 3), (64, 4), (48, 1), (32, 1), (64, 0)):
+            rsagpu.set_plan(limbs, kind, 0, 0, 0)
+        # every default CRT plan fits
+        for width in range(1, 65):
+            for kind in (1, 3, 4):
+                p = rsagpu.get_plan(width, kind)
+                pairs = 2 if kind == 1 and p.lanes_per_op >= 8 else 1
+                assert 2 * pairs * p.lds_bytes + 16 <= 160 * 1024, (width, kind, p)
+    finally:
+        for limbs, kind in ((64, 1), (64, 3), (64, 4), (48, 1), (32, 1), (64, 0)):
+            rsagpu.set_plan(limbs, kind, 0, 0, 0)
 
 
 def test_plan_lds_sizes():
