@@ -33,9 +33,10 @@ line carries
   encrypt:      the same batch's messages encrypted with e = 65537, with its
                 own rate, roofline, check and oracle comparison.
 
-Other workloads (--workload): rsa64, rsa1024 (full-d decryption, no CRT, and
-under `encrypt` the same messages' e = 65537 encryptions), enc2048 (e = 65537
-encryption of the default batch), mixed (32768 operations
+Other workloads (--workload): crt4096 (the plain CRT call on 4096-bit keys:
+16 keys, by default 1092 messages), rsa64, rsa1024 (full-d decryption, no CRT,
+and under `encrypt` the same messages' e = 65537 encryptions), enc2048
+(e = 65537 encryption of the default batch), mixed (32768 operations
 over 1024..4096-bit keys in one rsa_ops_batch call), serve (Poisson requests
 through the continuous-batching server: p50/p99 latency and throughput),
 paper (the paper's own Section 10 experiment: one-word keys n = 131*137 and
@@ -436,7 +437,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="crt2048",
-                    choices=["crt2048", "rsa64", "rsa1024", "enc2048", "mixed", "serve", "paper", "keygen",
+                    choices=["crt2048", "crt4096", "rsa64", "rsa1024", "enc2048", "mixed", "serve", "paper", "keygen",
                              "mulpeak"])
     ap.add_argument("--count", type=int, default=0, help="messages (0: the workload's size)")
     ap.add_argument("--cpu-sample", type=int, default=-1,
@@ -523,13 +524,17 @@ def main():
     cpu = None
     t0 = time.time()
 
-    if args.workload in ("crt2048", "enc2048"):
-        count = args.count or 16384
-        wl = W.workload_c3(count=count)
+    if args.workload in ("crt2048", "enc2048", "crt4096"):
+        if args.workload == "crt4096":
+            wl = W.workload_crt4096(count=args.count or 1092)
+            count = len(wl.ctxt)
+        else:
+            count = args.count or 16384
+            wl = W.workload_c3(count=count)
         L, h = wl.limbs, wl.limbs // 2
         print("# workload ready in %.1fs" % (time.time() - t0), file=sys.stderr, flush=True)
         n_h, e_h, d_h = tab(wl, "n", L), tab(wl, "e", L), tab(wl, "d", L)
-        if args.workload == "crt2048":
+        if args.workload in ("crt2048", "crt4096"):
             c = dev(wl.ctxt)
             p, q, dp, dq, qi = (dev(tab(wl, a, h)) for a in ("p", "q", "dp", "dq", "qinv"))
             out = torch.empty_like(c)
@@ -560,10 +565,12 @@ def main():
             ms_plain, _ = timed(plain, max(1, args.steps // 4), 1, torch)
             line["plain_one_key_per_launch"] = {"value": count / (ms_plain / 1e3), "ms_per_step": ms_plain,
                                                 "launches": len(per_key)}
-            line.update(metric=METRIC, unit="decryptions/s",
-                        config={"workload": "rsa2048-crt-decrypt", "keys": len(wl.keys), "messages": count,
-                                "modulus_bits": 32 * L, "radix_bits": plan.radix_bits,
-                                "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op})
+            line.update(metric=METRIC if args.workload == "crt2048" else
+                        "4096-bit modexp/sec (CRT decrypt) on 1 GPU", unit="decryptions/s",
+                        config={"workload": "rsa%d-crt-decrypt" % (32 * L), "keys": len(wl.keys),
+                                "messages": count, "modulus_bits": 32 * L, "radix_bits": plan.radix_bits,
+                                "window_bits": plan.window_bits, "lanes_per_op": plan.lanes_per_op,
+                                "waves_per_workgroup": 4 if plan.lanes_per_op >= 8 else 2})
             per_unit = unit_crt_products(h)
             line["roofline"] = roofline(per_unit * count, ms, "k_crt<%d,%d,%d>" % (plan.padded_limbs,
                                                                                    plan.lanes_per_op,
@@ -573,10 +580,11 @@ def main():
                 import oracle
                 cpu = cpu_baseline(oracle, wl.ctxt, d_h, n_h, out.cpu().numpy().view(np.uint32), "decryptions/s",
                                    "plain C^d mod n (no CRT)",
-                                   None if args.cpu_sample < 0 else min(args.cpu_sample, count))
+                                   None if args.cpu_sample < 0 else min(args.cpu_sample, count),
+                                   prefix=256 if L <= 64 else 32)
             line["encrypt"] = encrypt_half(wl, L, n_h, e_h,
                                            lambda x: rsagpu.decrypt_crt(x, p, q, dp, dq, qi))
-            if args.serve_seconds > 0:
+            if args.serve_seconds > 0 and args.workload == "crt2048":
                 sv = serve_leg(torch, np, rsagpu, W, args.serve_seconds, streams=args.serve_streams,
                                forks=args.serve_forks)
                 if sv["check"]["mismatches"]:

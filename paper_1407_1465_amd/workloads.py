@@ -369,6 +369,13 @@ def workload_c3(count: int = 16384, nkeys: int = 64) -> Workload:
     return single_size_workload("rsa2048-64keys", 2048, nkeys, count, SEED_BASE + 3)
 
 
+def workload_crt4096(count: int = 1092) -> Workload:
+    """4096-bit moduli, the 16 keys of the mixed workload's 4096-bit class,
+    messages round-robin; by default as many as that workload's 4096-bit
+    CRT decryptions."""
+    return single_size_workload("rsa4096-16keys", 4096, 16, count, SEED_BASE + 4)
+
+
 @dataclass
 class MixedWorkload:
     """Operations over keys of several sizes, laid out for rsa_ops_batch."""
