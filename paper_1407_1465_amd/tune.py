@@ -120,49 +120,93 @@ def candidate_plans(width: int, kind: int):
     return out
 
 
-def tune_batch(run, slots, reps: int = 3, passes: int = 1, tolerance: float = 0.005, knobs=()):
+def tune_batch(run, slots, reps: int = 3, passes: int = 1, tolerance: float = 0.005, knobs=(),
+               timer=None, confirm: int = 5):
     """Coordinate descent over the plans of `slots` [(width, kind), ...] for
     the batch that run() enqueues on torch's current stream: each candidate
     is installed and the batch timed (one warm-up, then `reps` runs between
     HIP events); a candidate replaces the slot's plan when it is faster by
-    more than `tolerance`.  `knobs` [(name, values, apply)] are further
-    settings tuned the same way after the plans (apply(value) installs one;
-    values[0] is the current one).  Returns ({(width, kind): (radix, lanes,
-    window), name: value, ...}, ms per call with the chosen settings)."""
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    more than `tolerance` in two timings in a row (one lucky timing does not
+    move the descent).  `knobs` [(name, values, apply)] are further settings
+    tuned the same way after the plans (apply(value) installs one; values[0]
+    is the current one).  At the end the starting settings and the chosen
+    ones are timed `confirm` times each, alternately, and the chosen ones are
+    kept only if their median is faster by more than `tolerance`; otherwise
+    the starting settings are restored.  `timer`, if given, replaces the HIP
+    event timing (a callable returning ms per call).  Returns ({(width,
+    kind): (radix, lanes, window), name: value, ...}, ms per call with the
+    settings in place)."""
+    if timer is None:
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def time_it() -> float:
-        run()
-        e0.record(stream)
-        for _ in range(reps):
+        def timer() -> float:
             run()
-        e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps
+            e0.record(stream)
+            for _ in range(reps):
+                run()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps
 
-    best = time_it()
-    chosen = {}
+    def plan_of(width, kind):
+        p = rsagpu.get_plan(width, kind)
+        return (p.radix_bits, p.lanes_per_op, p.window_bits)
+
+    def install(cfg):
+        for key, value in cfg.items():
+            if isinstance(key, tuple):
+                rsagpu.set_plan(key[0], key[1], *value)
+        for name, _, apply in knobs:
+            apply(cfg[name])
+
+    start = {(w, k): plan_of(w, k) for w, k in slots}
+    for name, values, _ in knobs:
+        start[name] = values[0]
+
+    def better(ms, best):
+        return ms < best * (1.0 - tolerance)
+
+    best = timer()
+    chosen = dict(start)
     for _ in range(passes):
         for width, kind in slots:
-            p = rsagpu.get_plan(width, kind)
-            cur = (p.radix_bits, p.lanes_per_op, p.window_bits)
+            cur = chosen[(width, kind)]
             for cand in candidate_plans(width, kind):
                 if cand == cur:
                     continue
                 rsagpu.set_plan(width, kind, *cand)
-                ms = time_it()
-                if ms < best * (1.0 - tolerance):
-                    best, cur = ms, cand
+                ms = timer()
+                if better(ms, best):
+                    ms2 = timer()
+                    if better(ms2, best):
+                        best, cur = max(ms, ms2), cand
             rsagpu.set_plan(width, kind, *cur)
             chosen[(width, kind)] = cur
         for name, values, apply in knobs:
-            cur = values[0]
-            for v in values[1:]:
+            cur = chosen[name]
+            for v in values:
+                if v == cur:
+                    continue
                 apply(v)
-                ms = time_it()
-                if ms < best * (1.0 - tolerance):
-                    best, cur = ms, v
+                ms = timer()
+                if better(ms, best):
+                    ms2 = timer()
+                    if better(ms2, best):
+                        best, cur = max(ms, ms2), v
             apply(cur)
             chosen[name] = cur
-    return chosen, best
+    if chosen == start:
+        return chosen, best
+    a, b = [], []
+    for _ in range(confirm):
+        install(start)
+        a.append(timer())
+        install(chosen)
+        b.append(timer())
+    a.sort()
+    b.sort()
+    if better(b[len(b) // 2], a[len(a) // 2]):
+        return chosen, b[len(b) // 2]
+    install(start)
+    return dict(start), a[len(a) // 2]
