@@ -134,10 +134,11 @@ int rsa_decrypt_crt_batch_static(const uint32_t *c, const uint32_t *p, const uin
  * radix (padded_limbs), lanes per exponentiation (G), limbs per lane
  * (padded_limbs / G), window width in exponent bits (a sliding window over
  * the 2^(window_bits-1) odd powers, paper Section 3.6.5) and the LDS bytes
- * per wave.  The CRT kernels run a wave per half: rsa_decrypt_crt_batch in
- * workgroups of one pair of waves, or of two pairs where lanes_per_op is 8
- * or 16 (one wave per SIMD of a CU), rsa_ops_batch in workgroups of one
- * pair, so a workgroup takes 2 or 4 times lds_bytes.
+ * per wave.  The CRT kernels run a wave per half, in workgroups of one
+ * pair of waves, or of two pairs (one wave per SIMD of a CU) where
+ * lanes_per_op is 8 or 16 in rsa_decrypt_crt_batch (kind 1) and in the
+ * bucket that ends a bulk rsa_ops_batch call (kind 4): a workgroup takes 2
+ * or 4 times lds_bytes.
  * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
  * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
  * operations inside rsa_ops_batch (separate plans: its buckets are smaller

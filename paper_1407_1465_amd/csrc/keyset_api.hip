@@ -422,13 +422,16 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         const int pkind = (kind == 1 && t == 0 && nops >= kBulkOps) ? 4 : kind + 2;
         Resolved r;
         if (!resolve(width, pkind, &r)) return RSA_ELIMBS;
-        int per = r.inst->blocks_per_cu(kind, r.w);
+        // the bucket that ends a bulk batch: two pairs of waves per
+        // workgroup where its halves have 8 or 16 lanes (see crt_pairs)
+        const int pairs = pkind == 4 ? crt_pairs(r.inst->G) : 1;
+        int per = r.inst->blocks_per_cu(kind, r.w, pairs);
         if (per <= 0) per = 1;
         const int blocks = per * cus;
         const bool fork = kind == 1 && t < nfork;
         hipStream_t s = fork ? fs->streams[t] : stream;
         if (fork && (e = hipStreamWaitEvent(s, fs->fork, 0)) != hipSuccess) return status_of(e);
-        const ops_launcher fn = kind == 0 ? r.inst->ops_enc : r.inst->ops_crt;
+        const ops_launcher fn = kind == 0 ? r.inst->ops_enc : (pairs > 1 ? r.inst->ops_crt_pairs : r.inst->ops_crt);
         e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b, counters + b,
                in_pool, out_pool, r.w, blocks, (kind == 1 && t == 0) ? 1 : 0, s);
         if (e != hipSuccess) return status_of(e);

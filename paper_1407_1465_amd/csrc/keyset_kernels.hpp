@@ -152,38 +152,41 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
 }
 
 // Bucket of CRT decryptions for keys of one width class: H limbs of radix
-// 2^B hold p and q.  A workgroup of two waves claims NG = 64 / G operations
-// at a time: wave 0 takes their halves modulo p, wave 1 those modulo q, one
-// operation per lane group, so a chunk of one key's operations (the bucket
-// lists are ordered by key) gives each wave a single exponent.  m_q reaches
-// wave 0 through wave 1's LDS region; wave 0 recombines and stores.
-template <int H, int G, int B>
-__global__ __launch_bounds__(128) void k_ops_crt(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
-                                                 const unsigned *__restrict__ list, const unsigned *count_p,
-                                                 unsigned *counter, const uint32_t *__restrict__ in_pool,
-                                                 uint32_t *out_pool, int w, int urgent)
+// 2^B hold p and q.  A workgroup of P pairs of waves (P = 1, or 2 for the
+// bucket that ends a bulk batch where a half has 8 or 16 lanes, see
+// crt_pairs) claims P * NG operations at a time (NG = 64 / G), each pair a
+// run of NG of them: the pair's wave 0 takes their halves modulo p, its wave
+// 1 those modulo q, one operation per lane group, so a run of one key's
+// operations (the bucket lists are ordered by key) gives each wave a single
+// exponent.  m_q reaches the pair's wave 0 through its wave 1's LDS region;
+// wave 0 recombines and stores.
+template <int H, int G, int B, int P>
+__global__ __launch_bounds__(128 * P) void k_ops_crt(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
+                                                     const unsigned *__restrict__ list, const unsigned *count_p,
+                                                     unsigned *counter, const uint32_t *__restrict__ in_pool,
+                                                     uint32_t *out_pool, int w, int urgent)
 {
     using Ar = Arith<H, G, B>;
     using Ly = Layout<H, G>;
     constexpr int L = H / G, NG = 64 / G;
     constexpr bool OWN = B != 32 && !standard_s29(H);     // constants not in the keyset's limb count
     __shared__ unsigned chunk;
-    const int half = (int)(threadIdx.x >> 6);
+    const int wave = (int)(threadIdx.x >> 6), pair = wave >> 1, half = wave & 1;
     const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
-    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + half * region;
-    uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + region;     // wave 1's region
+    uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + wave * region;
+    uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + (2 * pair + 1) * region;   // the pair's wave 1
     const int g = grp_index<G>(), r = grp_lane<G>();
     const unsigned count = *count_p;
     if (urgent) __builtin_amdgcn_s_setprio(2);
     for (;;) {
-        // Wave 0 reaches this barrier after Garner has read the previous
-        // chunk's m_q, and wave 1 reads `chunk` before the barrier below:
-        // neither the claim nor wave 1's next use of its region overtakes.
-        if (threadIdx.x == 0) chunk = atomicAdd(counter, (unsigned)NG);
+        // The wave 0s reach this barrier after Garner has read the previous
+        // chunk's m_q, and every wave reads `chunk` before the barrier below:
+        // neither the claim nor a wave 1's next use of its region overtakes.
+        if (threadIdx.x == 0) chunk = atomicAdd(counter, (unsigned)(P * NG));
         __syncthreads();
         const unsigned base = chunk;
-        if (base >= count) break;                     // the same for both waves
-        const unsigned idx = base + g;
+        if (base >= count) break;                     // the same for every wave
+        const unsigned idx = base + pair * NG + g;
         const bool live = idx < count;
         const OpDesc op = ops[live ? list[idx] : list[base]];
         const KeyDev &k = keys[op.key_id];

@@ -30,7 +30,7 @@ typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const 
                                    const unsigned *count, unsigned *counter, const uint32_t *in_pool,
                                    uint32_t *out_pool, int w, int blocks, int urgent, hipStream_t stream);
 // Workgroups of an ops kernel resident per CU at window w (occupancy query).
-typedef int (*ops_occupancy)(int kind, int w);
+typedef int (*ops_occupancy)(int kind, int w, int pairs);
 
 // Radix-2^29 limb counts of the width classes (29 * S >= 32 * width + 10, so
 // R > 2^10 n): the limb count a keyset's Montgomery constants are stored
@@ -74,16 +74,18 @@ inline size_t lds_bytes_for(int S, int G, int B, int w)
     return (size_t)lds_entries(B, G, w) * (size_t)S * (size_t)(64 / G) * 4u;
 }
 
-// p/q wave pairs per workgroup of the plain CRT kernel (k_crt).  A CU that
+// p/q wave pairs per CRT workgroup where a half has G lanes.  A CU that
 // receives a second two-wave workgroup while others have none has been
 // measured to run both on the same two SIMDs (a launch of 273 such
 // workgroups took 1.57x as long as one of 250), so where the waves hold few
 // messages (8 or 16 lanes per half: a batch of them is few workgroups, and
 // little LDS keeps several resident) a workgroup carries two pairs, one wave
-// per SIMD, and half as many workgroups cover a batch.  The ops-batch CRT
-// kernel keeps one pair: beside other buckets' waves, four-wave workgroups
-// wait longer for a CU with room on every SIMD (served requests' p99 latency
-// rose from 25 to 31-33 ms with them).
+// per SIMD, and half as many workgroups cover a batch.  This holds for the
+// plain CRT kernel (k_crt) and, in rsa_ops_batch, for the bucket that ends a
+// bulk batch (plan kind 4); its other CRT buckets keep one pair: beside
+// other buckets' waves a four-wave workgroup waits longer for a CU with room
+// on every SIMD (served requests' p99 latency rose from 25 to 31-33 ms with
+// two pairs in every bucket).
 __host__ __device__ constexpr int crt_pairs(int G) { return G >= 8 ? 2 : 1; }
 
 // LDS one workgroup may allocate on gfx950, and the CRT kernels' own LDS
@@ -121,7 +123,16 @@ hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned 
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                           int urgent, hipStream_t stream);
 
+// The ops-batch CRT kernel with crt_pairs(G) pairs per workgroup (the same
+// kernel as launch_ops_crt where that is 1).
 template <int S, int G, int B>
-int ops_blocks_per_cu(int kind, int w);
+hipError_t launch_ops_crt_pairs(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
+                                unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
+                                int urgent, hipStream_t stream);
+
+// Resident workgroups per CU of an ops-batch kernel (kind 0 encryption, 1
+// CRT with `pairs` pairs of waves).
+template <int S, int G, int B>
+int ops_blocks_per_cu(int kind, int w, int pairs);
 
 }  // namespace rsagpu

@@ -58,23 +58,47 @@ hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned 
                           int urgent, hipStream_t stream)
 {
     if (!crt_lds_fits(S, G, B, w, 1)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ops_crt<S, G, B>), dim3(blocks), dim3(128), 2 * lds_bytes_for(S, G, B, w), stream, keys,
+    hipLaunchKernelGGL((k_ops_crt<S, G, B, 1>), dim3(blocks), dim3(128), 2 * lds_bytes_for(S, G, B, w), stream, keys,
                        ops, list, count, counter, in_pool, out_pool, w, urgent);
     return hipGetLastError();
 }
 
 template <int S, int G, int B>
-int ops_blocks_per_cu(int kind, int w)
+hipError_t launch_ops_crt_pairs(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
+                                unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
+                                int urgent, hipStream_t stream)
+{
+    if constexpr (crt_pairs(G) == 1) {
+        return launch_ops_crt<S, G, B>(keys, ops, list, count, counter, in_pool, out_pool, w, blocks, urgent, stream);
+    } else {
+        constexpr int P = crt_pairs(G);
+        if (!crt_lds_fits(S, G, B, w, P)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_ops_crt<S, G, B, P>), dim3(blocks), dim3(128 * P), 2 * P * lds_bytes_for(S, G, B, w),
+                           stream, keys, ops, list, count, counter, in_pool, out_pool, w, urgent);
+        return hipGetLastError();
+    }
+}
+
+template <int S, int G, int B>
+int ops_blocks_per_cu(int kind, int w, int pairs)
 {
     int nb = 0;
     const size_t lds = lds_bytes_for(S, G, B, w);
     hipError_t e = hipErrorInvalidValue;
-    if (kind == 0)
+    if (kind == 0) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_enc<S, G, B>), 64,
                                                          lds);
-    else if constexpr (crt_instance(S, B))
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B>),
-                                                         128, 2 * lds);
+    } else if constexpr (crt_instance(S, B)) {
+        if constexpr (crt_pairs(G) > 1) {
+            if (pairs > 1)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B, crt_pairs(G)>), 128 * crt_pairs(G),
+                    2 * crt_pairs(G) * lds);
+        }
+        if (e != hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B, 1>),
+                                                             128, 2 * lds);
+    }
     return e == hipSuccess ? nb : 0;
 }
 
@@ -92,7 +116,7 @@ int ops_blocks_per_cu(int kind, int w)
     template hipError_t rsagpu::launch_ops_enc<S_, G_, B_>(                                                 \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
         const uint32_t *, uint32_t *, int, int, int, hipStream_t);                                          \
-    template int rsagpu::ops_blocks_per_cu<S_, G_, B_>(int, int);
+    template int rsagpu::ops_blocks_per_cu<S_, G_, B_>(int, int, int);
 
 #define RSAGPU_INSTANTIATE(B_, S_, G_)                                                                      \
     static_assert(rsagpu::crt_instance(S_, B_), "CRT launchers of an instance wider than any CRT half");    \
@@ -102,5 +126,8 @@ int ops_blocks_per_cu(int kind, int w)
                                                    const unsigned *, uint32_t *, size_t, int, int,          \
                                                    unsigned long long *, hipStream_t);                      \
     template hipError_t rsagpu::launch_ops_crt<S_, G_, B_>(                                                 \
+        const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
+        const uint32_t *, uint32_t *, int, int, int, hipStream_t);                                          \
+    template hipError_t rsagpu::launch_ops_crt_pairs<S_, G_, B_>(                                           \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \
         const uint32_t *, uint32_t *, int, int, int, hipStream_t);

@@ -15,7 +15,8 @@ struct Instance {
     setup_launcher setup;
     ops_launcher ops_enc;
     ops_launcher ops_crt;
-    int (*blocks_per_cu)(int kind, int w);
+    ops_launcher ops_crt_pairs;       // crt_pairs(G) pairs per workgroup (the bucket ending a bulk batch)
+    ops_occupancy blocks_per_cu;
 };
 
 // Width classes in 32-bit limbs and their radix-2^29 limb counts.

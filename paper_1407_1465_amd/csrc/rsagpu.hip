@@ -24,11 +24,18 @@ constexpr ops_launcher ops_crt_of()
     if constexpr (crt_instance(S, B)) return &launch_ops_crt<S, G, B>;
     else return nullptr;
 }
+template <int S, int G, int B>
+constexpr ops_launcher ops_crt_pairs_of()
+{
+    if constexpr (crt_instance(S, B)) return &launch_ops_crt_pairs<S, G, B>;
+    else return nullptr;
+}
 
 static const Instance kInstances[] = {
 #define X(B_, S_, G_)                                                                                     \
     {B_, S_, G_, &launch_modexp<S_, G_, B_>, crt_of<S_, G_, B_>(), &launch_setup<S_, G_, B_>,             \
-     &launch_ops_enc<S_, G_, B_>, ops_crt_of<S_, G_, B_>(), &ops_blocks_per_cu<S_, G_, B_>},
+     &launch_ops_enc<S_, G_, B_>, ops_crt_of<S_, G_, B_>(), ops_crt_pairs_of<S_, G_, B_>(),               \
+     &ops_blocks_per_cu<S_, G_, B_>},
 #include "instances.def"
 #undef X
 };
@@ -282,7 +289,7 @@ extern "C" int rsa_set_plan(int limbs, int kind, int radix_bits, int lanes_per_o
     if (!in || (crt_kind(kind) && !(in->crt && in->ops_crt))) return RSA_EINVAL;
     if (window_bits < 2 || window_bits > 7) return RSA_EINVAL;
     if (lds_bytes_for(in->S, in->G, in->B, window_bits) > 64 * 1024) return RSA_EINVAL;
-    if (crt_kind(kind) && !crt_lds_fits(in->S, in->G, in->B, window_bits, kind == 1 ? crt_pairs(in->G) : 1))
+    if (crt_kind(kind) && !crt_lds_fits(in->S, in->G, in->B, window_bits, kind == 3 ? 1 : crt_pairs(in->G)))
         return RSA_EINVAL;
     g_plan[kind][i].store(pack(Plan{radix_bits, lanes_per_op, window_bits}));
     return RSA_OK;

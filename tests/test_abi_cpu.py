@@ -129,17 +129,18 @@ def test_ops_batch_plans_are_separate():
 
 
 def test_crt_plans_fit_the_workgroup_lds():
-    """The plain CRT call runs two pairs of waves per workgroup where a half
-    has 8 or 16 lanes: its window tables must fit 160 KiB four times over
-    (plus 16 bytes).  The ops-batch CRT kinds run one pair (twice over), and
-    plain exponentiation one wave."""
+    """The plain CRT call (kind 1) and the bucket ending a bulk ops batch
+    (kind 4) run two pairs of waves per workgroup where a half has 8 or 16
+    lanes: their window tables must fit 160 KiB four times over (plus 16
+    bytes).  The other ops-batch CRT buckets (kind 3) run one pair (twice
+    over), and plain exponentiation one wave."""
     from paper_1407_1465_amd import rsagpu
     try:
-        rsagpu.set_plan(64, 1, 29, 16, 5)                           # 2048-bit halves: 4 x 20480 bytes
-        with pytest.raises(Exception):
-            rsagpu.set_plan(64, 1, 29, 16, 6)                       # 4 x 40960 + 16 > 160 KiB
-        for kind in (3, 4):
-            rsagpu.set_plan(64, kind, 29, 16, 6)                    # 2 x 40960 + 16
+        for kind in (1, 4):
+            rsagpu.set_plan(64, kind, 29, 16, 5)                    # 2048-bit halves: 4 x 20480 bytes
+            with pytest.raises(Exception):
+                rsagpu.set_plan(64, kind, 29, 16, 6)                # 4 x 40960 + 16 > 160 KiB
+        rsagpu.set_plan(64, 3, 29, 16, 6)                           # 2 x 40960 + 16
         rsagpu.set_plan(48, 1, 29, 8, 5)                            # 1536-bit halves: 4 x 28672
         with pytest.raises(Exception):
             rsagpu.set_plan(48, 1, 29, 8, 6)                        # 4 x 57344
@@ -152,7 +153,7 @@ def test_crt_plans_fit_the_workgroup_lds():
         for width in range(1, 65):
             for kind in (1, 3, 4):
                 p = rsagpu.get_plan(width, kind)
-                pairs = 2 if kind == 1 and p.lanes_per_op >= 8 else 1
+                pairs = 2 if kind in (1, 4) and p.lanes_per_op >= 8 else 1
                 assert 2 * pairs * p.lds_bytes + 16 <= 160 * 1024, (width, kind, p)
     finally:
         for limbs, kind in ((64, 1), (64, 3), (64, 4), (48, 1), (32, 1), (64, 0)):
