@@ -756,7 +756,8 @@ def main():
         ms_plain, _ = timed(plain, max(1, args.steps // 4), 1, torch)
         # each (size, kind) bucket of the batch alone, with the same plans
         # (a call that small takes kind 3 for its CRT bucket: for the widest
-        # one kind 3 holds kind 4's plan while it is timed)
+        # one kind 3 holds kind 4's plan while it is timed, and runs it with
+        # one pair of waves per workgroup, as kind 3 does)
         alone = {}
         limbs_of = np.array([wl.keys[i].limbs for i in wl.key_ids])
         sizes = sorted(set(limbs_of.tolist()), reverse=True)
