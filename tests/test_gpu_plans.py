@@ -211,3 +211,20 @@ def test_autotune_ops_plans_install_working_plans(bits, kind, count, plan_guard)
     bad = ops_batch_vs_oracle(keys, kinds, count, 7000 + bits)
     assert bad.size == 0, "%d-bit kind %d plan %s: %d bad" % (bits, kind, best, bad.size)
     assert rsagpu.device_errors() == 0
+
+
+def test_bulk_batch_ending_bucket_with_two_wave_pairs(plan_guard):
+    """The CRT bucket that ends a bulk batch (plan kind 4, at least 16384
+    operations) runs two p/q wave pairs per workgroup where its halves have
+    8 or 16 lanes: 16384 1024-bit decryptions on an 8-lane plan (the
+    16-lane one is covered by the full mixed workload), every output
+    against the oracle."""
+    rsagpu.set_plan(16, 4, 32, 8, 4)
+    plan_guard.append((16, 4))
+    p = rsagpu.get_plan(16, 4)
+    assert (p.radix_bits, p.lanes_per_op) == (32, 8)
+    keys = W.make_keys(1024, W.SEED_BASE + 4, 16)[:5]
+    count = 16384
+    bad = ops_batch_vs_oracle(keys, np.ones(count, dtype=np.int64), count, 4242)
+    assert bad.size == 0, "%d of %d differ, first %d" % (bad.size, count, bad[0])
+    assert rsagpu.device_errors() == 0
