@@ -1,7 +1,8 @@
 """The non-allocating CRT entry point (rsa_decrypt_crt_batch_static), called
 through the C ABI: bit-exact equal to rsa_decrypt_crt_batch on two calls in a
 row, the second with a smaller batch (the static scratch keeps the first
-call's contents), on 2048- and 1024-bit keys with ragged batch sizes, and
+call's contents), on 2048-, 1024- and 4096-bit keys (the last with two p/q
+wave pairs per workgroup) with ragged batch sizes, and
 captured into a HIP graph on a stream that never ran the call, replayed with
 eager work between replays."""
 import numpy as np
@@ -27,10 +28,11 @@ def crt_batch(bits, nkeys, count, seed):
     return keys, key_of, C, L
 
 
-@pytest.mark.parametrize("bits,nkeys,first,second", [(2048, 5, 1093, 301), (1024, 3, 517, 40)])
-def test_static_entry_point_equals_allocating_one(bits, nkeys, first, second):
+@pytest.mark.parametrize("bits,nkeys,first,second,seed", [(2048, 5, 1093, 301, 6148), (1024, 3, 517, 40, 5124),
+                                                           (4096, 16, 203, 37, W.SEED_BASE + 4)])
+def test_static_entry_point_equals_allocating_one(bits, nkeys, first, second, seed):
     rsagpu.init()
-    keys, key_of, C, L = crt_batch(bits, nkeys, first, 4100 + bits)
+    keys, key_of, C, L = crt_batch(bits, nkeys, first, seed)
     ops = [dev(a) for a in crt_operands(keys, key_of, L)]
     c = dev(C)
     want = rsagpu.decrypt_crt(c, *ops)
