@@ -160,6 +160,16 @@ def test_crt_plans_fit_the_workgroup_lds():
             rsagpu.set_plan(limbs, kind, 0, 0, 0)
 
 
+def test_plain_exponentiation_defaults_leave_room_for_two_waves_per_simd():
+    """A plain exponentiation workgroup is one wave; every default plan's
+    LDS lets a CU hold eight (two per SIMD), so a batch past one wave per
+    SIMD does not wait for a second round."""
+    from paper_1407_1465_amd import rsagpu
+    for width in range(1, 129):
+        p = rsagpu.get_plan(width, 0)
+        assert 8 * p.lds_bytes <= 160 * 1024, (width, p)
+
+
 def test_plan_lds_sizes():
     """LDS per 64-lane workgroup for a sliding window of w bits: the 2^(w-1)
     odd powers, plus one operand buffer where the multiplier is read from LDS
