@@ -90,10 +90,12 @@ int rsa_modexp_batch(const uint32_t *base, const uint32_t *exp, const uint32_t *
  * qinv = q^-1 mod p; p, q odd and > 1.  Violations are data errors.
  * c must be < p*q (it is the caller's ciphertext).
  * Messages under the same key are processed together (one exponent per
- * wave): for more than one workgroup's worth of messages the call orders
- * them by a hash of their key words, in a scratch buffer (4 bytes per
- * message + 256 KiB) that the library keeps for the current device and this
- * stream handle.  The first call on a stream, and a call with a larger
+ * wave): for more than one wave's worth of messages the call orders them by
+ * a hash of their key words, each key's run starting a wave of its own where
+ * the padding adds no round of waves to the launch, in a scratch buffer
+ * (4 bytes per slot of that order, the batch rounded up to whole waves and
+ * at most 2 waves per CU more, + 256 KiB) that the library keeps for the
+ * current device and this stream handle.  The first call on a stream, and a call with a larger
  * batch than that stream has seen, allocates it (hipMalloc; an outgrown
  * buffer is kept until the process ends, so graphs captured earlier stay
  * valid); later calls allocate nothing.  While `stream` is being captured
@@ -137,8 +139,10 @@ int rsa_decrypt_crt_batch_static(const uint32_t *c, const uint32_t *p, const uin
  * per wave.  The CRT kernels run a wave per half, in workgroups of one
  * pair of waves, or of two pairs (one wave per SIMD of a CU) where
  * lanes_per_op is 8 or 16 in rsa_decrypt_crt_batch (kind 1) and in the
- * bucket that ends a bulk rsa_ops_batch call (kind 4): a workgroup takes 2
- * or 4 times lds_bytes.
+ * bucket that ends a bulk rsa_ops_batch call (kind 4), and in
+ * rsa_decrypt_crt_batch calls of fewer lanes that need one to two one-pair
+ * workgroups per CU where the LDS holds two pairs: a workgroup takes 2 or 4
+ * times lds_bytes.
  * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
  * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
  * operations inside rsa_ops_batch (separate plans: its buckets are smaller

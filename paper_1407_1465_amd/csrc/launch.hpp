@@ -12,10 +12,14 @@ namespace rsagpu {
 typedef hipError_t (*modexp_launcher)(const uint32_t *base, const uint32_t *exp, const uint32_t *mod,
                                       uint32_t *out, size_t count, int limbs, int w,
                                       unsigned long long *errs, hipStream_t stream);
-// order: the processing order of the messages (count indices) or nullptr.
+// order: the processing order of the messages, `count` slots each holding a
+// message index or kOrderHole (a slot with no message), or nullptr (then
+// count is the number of messages, in the given order).  pairs: wave pairs
+// per workgroup (1 or 2, at least crt_pairs(G)).
 typedef hipError_t (*crt_launcher)(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
                                    const uint32_t *dq, const uint32_t *qinv, const unsigned *order, uint32_t *out,
-                                   size_t count, int hl, int w, unsigned long long *errs, hipStream_t stream);
+                                   size_t count, int hl, int w, int pairs, unsigned long long *errs,
+                                   hipStream_t stream);
 
 struct KeyDev;
 struct ModConsts;
@@ -29,7 +33,9 @@ typedef hipError_t (*setup_launcher)(const uint32_t *const *mods, const uint32_t
 typedef hipError_t (*ops_launcher)(const KeyDev *keys, const OpDesc *ops, const unsigned *list,
                                    const unsigned *count, unsigned *counter, const uint32_t *in_pool,
                                    uint32_t *out_pool, int w, int blocks, int urgent, hipStream_t stream);
-// Workgroups of an ops kernel resident per CU at window w (occupancy query).
+// Workgroups resident per CU at window w (occupancy query) of an ops-batch
+// kernel (kind 0 encryption, 1 CRT with `pairs` pairs of waves) or of the
+// plain CRT kernel (kind 2, one pair per workgroup).
 typedef int (*ops_occupancy)(int kind, int w, int pairs);
 
 // Radix-2^29 limb counts of the width classes (29 * S >= 32 * width + 10, so
@@ -80,13 +86,19 @@ inline size_t lds_bytes_for(int S, int G, int B, int w)
 // workgroups took 1.57x as long as one of 250), so where the waves hold few
 // messages (8 or 16 lanes per half: a batch of them is few workgroups, and
 // little LDS keeps several resident) a workgroup carries two pairs, one wave
-// per SIMD, and half as many workgroups cover a batch.  This holds for the
-// plain CRT kernel (k_crt) and, in rsa_ops_batch, for the bucket that ends a
-// bulk batch (plan kind 4); its other CRT buckets keep one pair: beside
+// per SIMD, and half as many workgroups cover a batch.  This is the least
+// the plain CRT kernel (k_crt) takes (rsa_decrypt_crt_batch picks 2 for
+// fewer lanes too where a batch needs one to two workgroups of one pair per
+// CU) and, in rsa_ops_batch, what the bucket that ends a bulk batch takes
+// (plan kind 4); its other CRT buckets keep one pair: beside
 // other buckets' waves a four-wave workgroup waits longer for a CU with room
 // on every SIMD (served requests' p99 latency rose from 25 to 31-33 ms with
 // two pairs in every bucket).
 __host__ __device__ constexpr int crt_pairs(int G) { return G >= 8 ? 2 : 1; }
+
+// A slot of a CRT processing order that holds no message (the padding that
+// lets each key's run of messages start a wave).
+constexpr unsigned kOrderHole = 0xFFFFFFFFu;
 
 // LDS one workgroup may allocate on gfx950, and the CRT kernels' own LDS
 // beyond the waves' regions (the ops kernel's claim word, aligned).
@@ -100,6 +112,7 @@ inline bool crt_lds_fits(int S, int G, int B, int w, int pairs)
     return 2 * (size_t)pairs * lds_bytes_for(S, G, B, w) + kCrtOwnLds <= kMaxGroupLds;
 }
 
+
 template <int S, int G, int B>
 hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32_t *mod, uint32_t *out,
                          size_t count, int limbs, int w, unsigned long long *errs, hipStream_t stream);
@@ -107,7 +120,7 @@ hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32
 template <int H, int G, int B>
 hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
                       const uint32_t *dq, const uint32_t *qinv, const unsigned *order, uint32_t *out, size_t count,
-                      int hl, int w, unsigned long long *errs, hipStream_t stream);
+                      int hl, int w, int pairs, unsigned long long *errs, hipStream_t stream);
 
 template <int S, int G, int B>
 hipError_t launch_setup(const uint32_t *const *mods, const uint32_t *const *mults, const int *words,
@@ -130,8 +143,7 @@ hipError_t launch_ops_crt_pairs(const KeyDev *keys, const OpDesc *ops, const uns
                                 unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                                 int urgent, hipStream_t stream);
 
-// Resident workgroups per CU of an ops-batch kernel (kind 0 encryption, 1
-// CRT with `pairs` pairs of waves).
+// Resident workgroups per CU (see ops_occupancy).
 template <int S, int G, int B>
 int ops_blocks_per_cu(int kind, int w, int pairs);
 

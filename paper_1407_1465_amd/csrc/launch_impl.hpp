@@ -20,11 +20,11 @@ hipError_t launch_modexp(const uint32_t *base, const uint32_t *exp, const uint32
 template <int H, int G, int B>
 hipError_t launch_crt(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
                       const uint32_t *dq, const uint32_t *qinv, const unsigned *order, uint32_t *out, size_t count,
-                      int hl, int w, unsigned long long *errs, hipStream_t stream)
+                      int hl, int w, int pairs, unsigned long long *errs, hipStream_t stream)
 {
-    constexpr int P = crt_pairs(G);
-    if (!crt_lds_fits(H, G, B, w, P)) return hipErrorInvalidValue;
-    const size_t ng = (64 / G) * P;            // messages per workgroup (P pairs of waves)
+    const int P = pairs;
+    if (P < crt_pairs(G) || P > 2 || !crt_lds_fits(H, G, B, w, P)) return hipErrorInvalidValue;
+    const size_t ng = (size_t)(64 / G) * P;    // slots per workgroup (P pairs of waves)
     const size_t blocks = (count + ng - 1) / ng;
     hipLaunchKernelGGL((k_crt<H, G, B>), dim3((unsigned)blocks), dim3(128 * P), 2 * P * lds_bytes_for(H, G, B, w),
                        stream, c, p, q, dp, dq, qinv, order, out, (unsigned long long)count, hl, w, errs);
@@ -89,6 +89,11 @@ int ops_blocks_per_cu(int kind, int w, int pairs)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_enc<S, G, B>), 64,
                                                          lds);
     } else if constexpr (crt_instance(S, B)) {
+        if (kind == 2) {
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_crt<S, G, B>), 128,
+                                                             2 * lds);
+            return e == hipSuccess ? nb : 0;
+        }
         if constexpr (crt_pairs(G) > 1) {
             if (pairs > 1)
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -123,7 +128,7 @@ int ops_blocks_per_cu(int kind, int w, int pairs)
     RSAGPU_INSTANTIATE_EXP(B_, S_, G_)                                                                      \
     template hipError_t rsagpu::launch_crt<S_, G_, B_>(const uint32_t *, const uint32_t *, const uint32_t *,    \
                                                    const uint32_t *, const uint32_t *, const uint32_t *,    \
-                                                   const unsigned *, uint32_t *, size_t, int, int,          \
+                                                   const unsigned *, uint32_t *, size_t, int, int, int,     \
                                                    unsigned long long *, hipStream_t);                      \
     template hipError_t rsagpu::launch_ops_crt<S_, G_, B_>(                                                 \
         const rsagpu::KeyDev *, const rsagpu::OpDesc *, const unsigned *, const unsigned *, unsigned *,     \

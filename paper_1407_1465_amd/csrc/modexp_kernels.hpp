@@ -629,15 +629,18 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_modexp(const uint3
 // modulo p, its wave 1 the halves modulo q, one message per lane group, so a
 // wave's exponents are all dp (or all dq) and, when its messages share a key,
 // equal (group_modexp then runs one schedule with symmetric squarings).  A
-// workgroup holds P = crt_pairs(G) pairs, which take consecutive runs of NG
-// messages: message i of pair j is order[(blockIdx.x * P + j) * NG + i] (the
-// identity without an order).  p, q, dp, dq, qinv have hl 32-bit words, c
+// workgroup holds P = blockDim.x / 128 pairs (1 or 2), which take consecutive
+// runs of NG slots: slot i of pair j is (blockIdx.x * P + j) * NG + i, and
+// holds message order[slot] (the identity without an order) unless that is
+// kOrderHole; groups of empty slots compute nothing that is stored, and a
+// workgroup of empty slots only returns at once.  p, q, dp, dq, qinv have hl
+// 32-bit words, c
 // and the result 2*hl; H limbs of radix 2^B hold a half (B*H >= 32*hl).
 // Each wave works in its own LDS region; m_q and its validity reach the
 // pair's wave 0 through its wave 1's region, and wave 0 recombines (Garner)
 // and stores.
 template <int H, int G, int B>
-__global__ __launch_bounds__(128 * crt_pairs(G)) void k_crt(
+__global__ __launch_bounds__(256) void k_crt(
     const uint32_t *__restrict__ c, const uint32_t *__restrict__ p, const uint32_t *__restrict__ q,
     const uint32_t *__restrict__ dp, const uint32_t *__restrict__ dq, const uint32_t *__restrict__ qinv,
     const unsigned *__restrict__ order, uint32_t *out, unsigned long long count, int hl, int w,
@@ -645,15 +648,31 @@ __global__ __launch_bounds__(128 * crt_pairs(G)) void k_crt(
 {
     using Ar = Arith<H, G, B>;
     using Ly = Layout<H, G>;
-    constexpr int L = H / G, NG = 64 / G, P = crt_pairs(G);
+    constexpr int L = H / G, NG = 64 / G;
+    const int P = (int)(blockDim.x >> 7);
     const int wave = (int)(threadIdx.x >> 6), pair = wave >> 1, half = wave & 1;
     const size_t region = (size_t)lds_entries(B, G, w) * Ly::WORDS;
     uint32_t *lds = reinterpret_cast<uint32_t *>(rsagpu_lds) + wave * region;
     uint32_t *qlds = reinterpret_cast<uint32_t *>(rsagpu_lds) + (2 * pair + 1) * region;   // the pair's wave 1
     const int g = grp_index<G>(), r = grp_lane<G>();
     const unsigned long long slot = ((unsigned long long)blockIdx.x * P + pair) * NG + g;
-    const bool live = slot < count;
-    const unsigned long long msg = live ? (order ? (unsigned long long)order[slot] : slot) : 0ull;
+    bool live = slot < count;
+    unsigned long long msg = slot;
+    if (live && order) {
+        const unsigned o = order[slot];
+        live = o != kOrderHole;
+        msg = o;
+    }
+    if (!live) msg = 0ull;
+    {   // a workgroup of empty slots only returns at once (every wave finds so alike)
+        const unsigned long long first = (unsigned long long)blockIdx.x * P * NG;
+        bool any = false;
+        for (int k = (int)__lane_id(); k < P * NG; k += 64) {
+            const unsigned long long s = first + (unsigned)k;
+            any = any || (s < count && (!order || order[s] != kOrderHole));
+        }
+        if (__ballot(any) == 0) return;
+    }
     const size_t hoff = live ? (size_t)msg * (size_t)hl : 0;
     const size_t foff = 2 * hoff;
     const int full = 2 * hl;

@@ -3,8 +3,15 @@
 // mostly hold one key's halves (one exponent per wave: one schedule, symmetric
 // squarings).  A counting sort of the messages by a hash of their key words
 // (p, dp, dq) into kBuckets = 2^16 buckets; distinct keys that share a
-// bucket only share waves, which then take the per-group schedule.  The order changes
-// which messages share a wave, never a result.
+// bucket only share waves, which then take the per-group schedule.  The
+// order has `slots` >= count entries, free ones holding kOrderHole.  When
+// the buckets' runs, each rounded up to a whole number of waves (ng
+// messages), fit in the slots, every run starts a wave of its own: a key
+// whose message count is not a multiple of ng then leaves a partly empty
+// wave rather than one shared with the next key, which would take the
+// slower per-group schedule and hold the whole launch back.  Otherwise the
+// runs follow each other with no gaps.  The order changes which messages
+// share a wave, never a result.
 #include "registry.hpp"
 
 #include <hip/hip_runtime.h>
@@ -33,10 +40,12 @@ __device__ __forceinline__ uint32_t key_bucket(const uint32_t *p, const uint32_t
     return h >> (32 - kBucketBits);
 }
 
-__global__ void k_order_clear(unsigned *cnt)
+__global__ void k_order_clear(unsigned *cnt, unsigned *order, unsigned long long slots)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < kBuckets) cnt[t] = 0u;          // a fill kernel, not a memset: safe to capture in a graph
+    // fill kernels, not memsets: safe to capture in a graph
+    const unsigned long long t = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (unsigned long long)kBuckets) cnt[t] = 0u;
+    if (t < slots) order[t] = kOrderHole;
 }
 
 __global__ void k_order_count(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, unsigned long long count,
@@ -47,34 +56,63 @@ __global__ void k_order_count(const uint32_t *p, const uint32_t *dp, const uint3
     atomicAdd(&cnt[key_bucket(p, dp, dq, i, hl)], 1u);
 }
 
-// Exclusive prefix sum of the bucket counts, in place, in an order of the
-// buckets that keeps the loads coalesced: thread t owns buckets t, t + 1024,
-// t + 2048, ... and the threads' runs follow each other (any order of the
-// buckets groups the messages the same way).  One workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_order_scan(unsigned *cnt)
+// Start of every bucket's run: the exclusive prefix sum of the bucket
+// counts, each rounded up to a multiple of ng (a power of two; 1 rounds
+// nothing) when the rounded runs fit in `slots`, else of the counts
+// themselves; in place.  The sums run over an order of the buckets that
+// keeps the loads coalesced: thread t owns buckets t, t + 1024, t + 2048,
+// ... and the threads' runs follow each other (any order of the buckets
+// groups the messages the same way).  One workgroup of 1024 threads: each
+// sums its buckets, a wave scans its threads' sums with lane shuffles,
+// every thread adds the totals of the waves before its own and reads its
+// buckets again to write their starts (kept in registers, the counts would
+// spill).  The caller
+// keeps the rounded total below 2^32.
+__global__ __launch_bounds__(1024) void k_order_scan(unsigned *cnt, unsigned ng, unsigned slots)
 {
-    constexpr int PER = kBuckets / 1024;
-    __shared__ unsigned part[1024];
-    const int t = threadIdx.x;
-    unsigned v[PER], s = 0;
-#pragma unroll
+    constexpr int PER = kBuckets / 1024, WAVES = 1024 / 64;
+    __shared__ unsigned wsum[WAVES], wpsum[WAVES];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const unsigned mask = ng - 1u;
+    unsigned s = 0u, ps = 0u;
+#pragma unroll 16
     for (int k = 0; k < PER; ++k) {
-        v[k] = cnt[k * 1024 + t];
-        s += v[k];
+        const unsigned v = cnt[k * 1024 + t];
+        s += v;
+        ps += (v + mask) & ~mask;
     }
-    part[t] = s;
+    unsigned is = s, ips = ps;                  // inclusive scans within the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned a = __shfl_up(is, o), b = __shfl_up(ips, o);
+        if (lane >= o) {
+            is += a;
+            ips += b;
+        }
+    }
+    if (lane == 63) {
+        wsum[wv] = is;
+        wpsum[wv] = ips;
+    }
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {       // inclusive scan of the partial sums
-        const unsigned add = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
-    }
-    unsigned run = part[t] - s;
+    unsigned base = 0u, pbase = 0u, ptot = 0u;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
+    for (int k = 0; k < WAVES; ++k) {
+        const unsigned a = wsum[k], b = wpsum[k];
+        if (k < wv) {
+            base += a;
+            pbase += b;
+        }
+        ptot += b;
+    }
+    const bool pad = ptot <= slots;
+    unsigned run = pad ? pbase + ips - ps : base + is - s;
+    const unsigned keep = pad ? ~mask : ~0u, add = pad ? mask : 0u;
+#pragma unroll 16
+    for (int k = 0; k < PER; ++k) {             // the counts again (cached), each replaced by its run's start
+        const unsigned v = cnt[k * 1024 + t];
         cnt[k * 1024 + t] = run;
-        run += v[k];
+        run += (v + add) & keep;
     }
 }
 
@@ -88,16 +126,36 @@ __global__ void k_order_place(const uint32_t *p, const uint32_t *dp, const uint3
 }
 
 static hipError_t launch_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
-                               unsigned *cnt, unsigned *order, hipStream_t stream)
+                               size_t ng, size_t slots, unsigned *cnt, unsigned *order, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((count + 255) / 256);
-    hipLaunchKernelGGL(k_order_clear, dim3(kBuckets / 256), dim3(256), 0, stream, cnt);
+    const size_t fill = slots > (size_t)kBuckets ? slots : (size_t)kBuckets;
+    hipLaunchKernelGGL(k_order_clear, dim3((unsigned)((fill + 255) / 256)), dim3(256), 0, stream, cnt, order,
+                       (unsigned long long)slots);
     hipLaunchKernelGGL(k_order_count, dim3(blocks), dim3(256), 0, stream, p, dp, dq, (unsigned long long)count, hl,
                        cnt);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, stream, cnt);
+    // the rounded runs total at most count + kBuckets * (ng - 1): no rounding
+    // where that could pass 2^32
+    const unsigned round_to = count + (size_t)kBuckets * ng <= (size_t)0xFFFFFFFFu ? (unsigned)ng : 1u;
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, stream, cnt, round_to, (unsigned)slots);
     hipLaunchKernelGGL(k_order_place, dim3(blocks), dim3(256), 0, stream, p, dp, dq, (unsigned long long)count, hl,
                        cnt, order);
     return hipGetLastError();
+}
+
+size_t key_order_slots(size_t count, size_t ng, size_t cus)
+{
+    const size_t waves = (count + ng - 1) / ng;                       // wave pairs of the dense order
+    const size_t round = 2 * (cus ? cus : 1);
+    const size_t up = waves <= round / 2 ? round / 2 : (waves + round - 1) / round * round;
+    const size_t keys = count < (size_t)kBuckets ? count : (size_t)kBuckets;
+    const size_t most = waves + keys;           // the padded runs never take more
+    return (up < most ? up : most) * ng;
+}
+
+static bool order_args_ok(size_t count, size_t ng, size_t slots)
+{
+    return ng > 0 && (ng & (ng - 1)) == 0 && slots >= count && slots < (size_t)kOrderHole;
 }
 
 // Scratch of the plain CRT call: one buffer per (device, stream handle),
@@ -119,11 +177,11 @@ std::vector<StreamScratch> g_scratch;
 std::vector<void *> g_outgrown;
 }  // namespace
 
-size_t key_order_bytes(size_t count) { return (count + kBuckets) * sizeof(unsigned); }
+size_t key_order_bytes(size_t slots) { return (slots + kBuckets) * sizeof(unsigned); }
 
 // Scratch of the non-allocating CRT call: static device memory (one copy per
 // device, held until the process ends) for the bucket counters and the order
-// of up to kStaticOrderMax messages.  Host code never names the array in a
+// of up to kStaticOrderMax slots.  Host code never names the array in a
 // launch: its device address is looked up once per device (order_static_init)
 // and that address is what the kernels receive.  Every call on a device
 // shares the array, so such calls must not overlap in time on one device.
@@ -150,10 +208,12 @@ int order_static_init(int dev)
 }
 
 unsigned *key_order_static(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
-                           hipStream_t stream)
+                           size_t ng, size_t slots, hipStream_t stream)
 {
     int dev = 0;
-    if (count > kStaticOrderMax || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return nullptr;
+    if (slots > kStaticOrderMax || !order_args_ok(count, ng, slots) || hipGetDevice(&dev) != hipSuccess || dev < 0 ||
+        dev >= kMaxDev)
+        return nullptr;
     unsigned *cnt = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_static_mu);
@@ -161,17 +221,17 @@ unsigned *key_order_static(const uint32_t *p, const uint32_t *dp, const uint32_t
     }
     if (!cnt) return nullptr;
     unsigned *order = cnt + kBuckets;
-    if (launch_order(p, dp, dq, count, hl, cnt, order, stream) != hipSuccess) return nullptr;
+    if (launch_order(p, dp, dq, count, hl, ng, slots, cnt, order, stream) != hipSuccess) return nullptr;
     return order;
 }
 
-unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
-                    hipStream_t stream)
+unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl, size_t ng,
+                    size_t slots, hipStream_t stream)
 {
-    if (count > 0xFFFFFFFFull) return nullptr;
+    if (!order_args_ok(count, ng, slots)) return nullptr;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    const size_t need = key_order_bytes(count);
+    const size_t need = key_order_bytes(slots);
     void *mem = nullptr;
     {
         std::lock_guard<std::mutex> lock(g_scratch_mu);
@@ -203,7 +263,7 @@ unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, s
         }
     }
     unsigned *cnt = static_cast<unsigned *>(mem), *order = cnt + kBuckets;
-    if (launch_order(p, dp, dq, count, hl, cnt, order, stream) != hipSuccess) return nullptr;
+    if (launch_order(p, dp, dq, count, hl, ng, slots, cnt, order, stream) != hipSuccess) return nullptr;
     return order;
 }
 

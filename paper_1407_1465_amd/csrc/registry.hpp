@@ -40,27 +40,38 @@ bool resolve(int limbs, int kind, Resolved *r);
 static const size_t kBulkOps = 16384;
 
 // Processing order of a plain CRT batch that puts messages under the same key
-// next to each other (device array of count indices), or nullptr to keep the
-// given order.  The scratch (key_order_bytes(count)) is the library's buffer
-// for this device and stream handle, made or grown on first need (never while
-// the stream is being captured: the given order is kept then).
-size_t key_order_bytes(size_t count);
-unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
-                    hipStream_t stream);
+// next to each other: a device array of `slots` entries, each a message index
+// or kOrderHole, every one of the count messages in exactly one; nullptr to
+// keep the given order.  ng (a power of two) is the messages of one wave;
+// each key's run starts a wave when the runs so rounded up fit in the slots.
+// key_order_slots gives the slots to ask for on a device of `cus` compute
+// units: the dense order's wave pairs rounded up to cus (one pair per CU) if
+// they fit in that, else to a multiple of 2 cus (one wave per SIMD), so that
+// the padding does not change the launch's shape, and never more than the
+// padded runs can take.  The scratch (key_order_bytes(slots))
+// is the library's buffer for this device and stream handle, made or grown
+// on first need (never while the stream is being captured: the given order
+// is kept then).
+size_t key_order_slots(size_t count, size_t ng, size_t cus);
+size_t key_order_bytes(size_t slots);
+unsigned *key_order(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl, size_t ng,
+                    size_t slots, hipStream_t stream);
 
 // The same order in the library's static device scratch (no allocation):
 // order_static_init looks up the scratch's address on device `dev` (once per
-// device, 0 on success); key_order_static then returns the order of up to
-// kStaticOrderMax messages, or nullptr (not set up, too many messages, or a
-// launch failure).  Calls on one device share the scratch.
+// device, 0 on success); key_order_static then returns the order in up to
+// kStaticOrderMax slots, or nullptr (not set up, too many slots, or a launch
+// failure).  Calls on one device share the scratch.
 static const size_t kStaticOrderMax = (size_t)1 << 20;
 int order_static_init(int dev);
 unsigned *key_order_static(const uint32_t *p, const uint32_t *dp, const uint32_t *dq, size_t count, int hl,
-                           hipStream_t stream);
+                           size_t ng, size_t slots, hipStream_t stream);
 
 // Per-device data-error counter: two words of static device memory (the
 // count, and the value rsa_device_errors last took), looked up once per device.
-int device_state(unsigned long long **errs);
+// device_state also gives the current device's compute units (cus, if not
+// null).
+int device_state(unsigned long long **errs, int *cus = nullptr);
 int status_of(hipError_t e);
 
 }  // namespace rsagpu

@@ -171,9 +171,10 @@ static __device__ __align__(256) unsigned long long g_err_words[2];
 
 static const int kMaxDevices = 64;
 static unsigned long long *g_errs[kMaxDevices];
+static int g_cus[kMaxDevices];
 static std::mutex g_dev_mutex;
 
-int device_state(unsigned long long **errs)
+int device_state(unsigned long long **errs, int *cus)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RSA_EHIP;
@@ -183,9 +184,16 @@ int device_state(unsigned long long **errs)
         if (hipGetSymbolAddress(&p, HIP_SYMBOL(g_err_words)) != hipSuccess || !p) return RSA_EHIP;
         // the non-allocating CRT call's static scratch on this device
         if (order_static_init(dev) != 0) return RSA_EHIP;
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) {
+            (void)hipGetLastError();
+            n = 1;
+        }
+        g_cus[dev] = n;
         g_errs[dev] = static_cast<unsigned long long *>(p);
     }
     *errs = g_errs[dev];
+    if (cus) *cus = g_cus[dev];
     return RSA_OK;
 }
 
@@ -224,6 +232,35 @@ extern "C" int rsa_modexp_batch(const uint32_t *base, const uint32_t *exp, const
     return status_of(r.inst->modexp(base, exp, mod, out, count, limbs, r.w, errs, stream));
 }
 
+// Wave pairs per workgroup of a plain CRT launch of `count` messages:
+// crt_pairs(G), or two for fewer lanes where the messages need more than one
+// and at most two workgroups of one pair per CU (the key-grouped order's
+// padding stays within that, see key_order_slots) and the kernel's occupancy
+// would let a CU take a second one (one-pair workgroups beyond one per CU
+// have been measured to share SIMDs: 8736 1024-bit messages, 273
+// workgroups, took 1.12 ms against 0.73 ms in workgroups of two pairs, one
+// wave per SIMD).  Where the launch fits one one-pair workgroup per CU, or
+// fills every SIMD anyway, one pair measured 1-6% faster.
+static const int kMaxCrtW = 8;
+static std::atomic<int> g_crt_occ[sizeof(kInstances) / sizeof(kInstances[0])][kMaxCrtW];
+
+static int plain_crt_launch_pairs(const Instance *in, int w, size_t count, int cus)
+{
+    if (crt_pairs(in->G) > 1) return crt_pairs(in->G);
+    const size_t pairs = (count + 64 / in->G - 1) / (64 / in->G);
+    if (pairs <= (size_t)cus || pairs > 2 * (size_t)cus || w < 1 || w >= kMaxCrtW ||
+        !crt_lds_fits(in->S, in->G, in->B, w, 2))
+        return 1;
+    std::atomic<int> &cached = g_crt_occ[in - kInstances][w];
+    int occ = cached.load(std::memory_order_relaxed);
+    if (occ == 0) {
+        occ = in->blocks_per_cu(2, w, 1);
+        if (occ < 1) occ = -1;                  // unknown: keep one pair
+        cached.store(occ, std::memory_order_relaxed);
+    }
+    return occ > 2 ? 2 : 1;
+}
+
 extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const uint32_t *q, const uint32_t *dp,
                                      const uint32_t *dq, const uint32_t *qinv, uint32_t *out, size_t count,
                                      int limbs, hipStream_t stream)
@@ -236,11 +273,19 @@ extern "C" int rsa_decrypt_crt_batch(const uint32_t *c, const uint32_t *p, const
     const size_t ng = 64 / r.inst->G;
     if ((count + ng - 1) / ng > 0x7FFFFFFFull) return RSA_EINVAL;
     unsigned long long *errs = nullptr;
-    const int st = device_state(&errs);
+    int cus = 1;
+    const int st = device_state(&errs, &cus);
     if (st != RSA_OK) return st;
-    // more than one workgroup: process the messages grouped by key
-    const unsigned *order = count > ng ? key_order(p, dp, dq, count, limbs / 2, stream) : nullptr;
-    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, count, limbs / 2, r.w, errs, stream));
+    // more than one wave's worth of messages: process them grouped by key
+    size_t slots = count;
+    const unsigned *order = nullptr;
+    if (count > ng) {
+        slots = key_order_slots(count, ng, (size_t)cus);
+        order = key_order(p, dp, dq, count, limbs / 2, ng, slots, stream);
+        if (!order) slots = count;
+    }
+    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, slots, limbs / 2, r.w,
+                                 plain_crt_launch_pairs(r.inst, r.w, count, cus), errs, stream));
 }
 
 static_assert(kStaticOrderMax == RSA_CRT_STATIC_MAX_COUNT, "static scratch size and its public limit agree");
@@ -257,11 +302,18 @@ extern "C" int rsa_decrypt_crt_batch_static(const uint32_t *c, const uint32_t *p
     if (!resolve(limbs / 2, 1, &r)) return RSA_ELIMBS;
     const size_t ng = 64 / r.inst->G;
     unsigned long long *errs = nullptr;
-    const int st = device_state(&errs);
+    int cus = 1;
+    const int st = device_state(&errs, &cus);
     if (st != RSA_OK) return st;
+    size_t slots = count;
     const unsigned *order = nullptr;
-    if (count > ng && !(order = key_order_static(p, dp, dq, count, limbs / 2, stream))) return RSA_EHIP;
-    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, count, limbs / 2, r.w, errs, stream));
+    if (count > ng) {
+        const size_t want = key_order_slots(count, ng, (size_t)cus);
+        slots = want < kStaticOrderMax ? want : kStaticOrderMax;    // >= count
+        if (!(order = key_order_static(p, dp, dq, count, limbs / 2, ng, slots, stream))) return RSA_EHIP;
+    }
+    return status_of(r.inst->crt(c, p, q, dp, dq, qinv, order, out, slots, limbs / 2, r.w,
+                                 plain_crt_launch_pairs(r.inst, r.w, count, cus), errs, stream));
 }
 
 extern "C" int rsa_get_plan(int limbs, int kind, rsa_plan *plan)

@@ -210,6 +210,33 @@ def test_crt_grouped_by_key_with_data_errors(bits):
     assert rsagpu.device_errors() == 2
 
 
+@pytest.mark.parametrize("bits,runs", [
+    (256, [37, 64, 100, 1, 70, 129]),        # runs that are not whole waves: each starts a wave of its own
+    (2048, [33, 31, 64, 5, 96]),
+    (128, [1] * 600),                        # 600 keys: padded runs would not fit, the order stays dense
+])
+def test_crt_key_runs_of_any_length(bits, runs):
+    """Messages under several keys, shuffled, with per-key counts that are
+    not multiples of a wave's messages (the key-grouped order pads each
+    key's run to whole waves where the padding fits the launch, and packs
+    the runs back to back where it does not): every element equals the
+    oracle, and the static-scratch call returns the same."""
+    keys = W.make_keys(bits, 13 + bits + len(runs), len(runs))
+    L = keys[0].limbs
+    key_of = np.repeat(np.arange(len(runs)), runs)
+    np.random.default_rng(bits).shuffle(key_of)
+    r = random.Random(bits + 3)
+    C = W.ints_to_limbs([r.randrange(keys[k].n) for k in key_of], L)
+    ops = [dev(a) for a in crt_operands(keys, key_of, L)]
+    out = host(rsagpu.decrypt_crt(dev(C), *ops))
+    want = oracle_modexp(C, full_operands(keys, key_of, L, "d"), full_operands(keys, key_of, L, "n"))
+    wrong = np.nonzero((out != want).any(axis=1))[0]
+    assert wrong.size == 0, "%d mismatches, first at %d" % (wrong.size, wrong[0])
+    static = host(rsagpu.decrypt_crt_static(dev(C), *ops, out=torch.empty_like(dev(C))))
+    assert np.array_equal(static, out)
+    assert rsagpu.device_errors() == 0
+
+
 @pytest.mark.parametrize("table", [1, 2])
 def test_paper_table_keys_round_trip(table):
     """The paper's Section 10 experiment on one-word keys: every encryption
