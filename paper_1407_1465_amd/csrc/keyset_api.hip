@@ -24,9 +24,13 @@ static const size_t kWsHeader = (2 * kMaxBuckets + (size_t)kMaxBuckets * kKeySlo
 //
 // Operations go into buckets of one (width class of the key, kind), each
 // list ordered by key id (a counting sort over id mod kKeySlots), so that
-// a bucket kernel's chunks hold one key's operations.  Invalid operations
-// (kind, key id, or an input/output range outside its pool) are counted as
-// data errors and dropped.
+// a bucket kernel's chunks hold one key's operations.  In a CRT bucket each
+// key slot's run starts a wave of its own where the runs, rounded up to
+// whole waves, fit the list: the gaps hold kOrderHole, and a wave that would
+// have taken the end of one key's run and the start of the next (two
+// exponents: the slower per-group schedule) takes the end alone.  Invalid
+// operations (kind, key id, or an input/output range outside its pool) are
+// counted as data errors and dropped.
 
 __global__ void k_bucket_clear(unsigned *hdr)
 {
@@ -61,24 +65,62 @@ __global__ void k_bucket_count(const OpDesc *__restrict__ ops, unsigned long lon
     atomicAdd(&slots[b * kKeySlots + (op.key_id % kKeySlots)], 1u);
 }
 
-// One workgroup per bucket: exclusive prefix sum of its key-slot counts (in
-// place: they become the list cursors) and the bucket's size.
-__global__ __launch_bounds__(kKeySlots) void k_bucket_scan(unsigned *counts, unsigned *slots)
+// Per bucket, the length its key slots' runs are rounded up to: the
+// operations of one wave of its kernel for a CRT bucket, else 1 (a power of
+// two).
+struct BucketUnits {
+    unsigned u[kMaxBuckets];
+};
+
+// One workgroup per bucket: exclusive prefix sum of its key-slot counts, each
+// rounded up to the bucket's unit when the rounded runs fit in the list's
+// `cap` entries, else as they are (in place: they become the list cursors);
+// the bucket's size (holes included); kOrderHole in the gaps.  Each wave
+// scans its threads' counts with lane shuffles and every thread adds the
+// totals of the waves before its own.  The caller keeps the rounded total
+// below 2^32.
+__global__ __launch_bounds__(kKeySlots) void k_bucket_scan(unsigned *counts, unsigned *slots, unsigned *lists,
+                                                           unsigned long long cap, BucketUnits units)
 {
-    __shared__ unsigned part[kKeySlots];
-    const int t = threadIdx.x;
+    constexpr int WAVES = kKeySlots / 64;
+    __shared__ unsigned wsum[WAVES], wpsum[WAVES];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const unsigned mask = units.u[blockIdx.x] - 1u;
     unsigned *sl = slots + (size_t)blockIdx.x * kKeySlots;
-    const unsigned v = sl[t];
-    part[t] = v;
-    __syncthreads();
-    for (int o = 1; o < kKeySlots; o <<= 1) {
-        const unsigned add = t >= o ? part[t - o] : 0u;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
+    const unsigned v = sl[t], pv = (v + mask) & ~mask;
+    unsigned is = v, ips = pv;                  // inclusive scans within the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned a = __shfl_up(is, o), b = __shfl_up(ips, o);
+        if (lane >= o) {
+            is += a;
+            ips += b;
+        }
     }
-    sl[t] = part[t] - v;
-    if (t == kKeySlots - 1) counts[blockIdx.x] = part[t];
+    if (lane == 63) {
+        wsum[wv] = is;
+        wpsum[wv] = ips;
+    }
+    __syncthreads();
+    unsigned base = 0u, pbase = 0u, tot = 0u, ptot = 0u;
+#pragma unroll
+    for (int k = 0; k < WAVES; ++k) {
+        const unsigned a = wsum[k], b = wpsum[k];
+        if (k < wv) {
+            base += a;
+            pbase += b;
+        }
+        tot += a;
+        ptot += b;
+    }
+    const bool pad = (unsigned long long)ptot <= cap;
+    const unsigned start = pad ? pbase + ips - pv : base + is - v;
+    sl[t] = start;
+    if (t == kKeySlots - 1) counts[blockIdx.x] = pad ? ptot : tot;
+    if (pad) {
+        unsigned *l = lists + (unsigned long long)blockIdx.x * cap + start;
+        for (unsigned i = v; i < pv; ++i) l[i] = kOrderHole;
+    }
 }
 
 __global__ void k_bucket_place(const OpDesc *__restrict__ ops, unsigned long long nops,
@@ -349,13 +391,44 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         nkeys = ks->nkeys;
         mask = ks->class_mask;
     }
+    // Bucket order and plans.  The CRT buckets of the widest classes are the
+    // longest (their operations are long dependency chains that a bucket's
+    // waves cannot shorten), so each of them gets a keyset stream of its own;
+    // the remaining buckets (narrower CRT classes, then all encryptions,
+    // widest first) follow each other on the caller's stream, beside them,
+    // which then waits for the keyset streams.  The widest CRT bucket's
+    // waves also raise their issue priority: every call ends with its
+    // operations, whose chains are the longest, so on a SIMD shared with other
+    // buckets' waves they issue first.
+    int order[kMaxBuckets], nb = 0;
+    for (int kind = 1; kind >= 0; --kind)
+        for (int cls = num_classes() - 1; cls >= 0; --cls)
+            if (mask & (1u << cls)) order[nb++] = cls * 2 + kind;
+    Resolved plan[kMaxBuckets];
+    int pairs[kMaxBuckets];
+    BucketUnits units;
+    for (int b = 0; b < kMaxBuckets; ++b) units.u[b] = 1u;
+    // rounded runs total at most nops + kKeySlots * 63 per bucket: kept 32-bit
+    const bool round_runs = nops + (size_t)kKeySlots * 64 <= (size_t)0xFFFFFFFFu;
+    for (int t = 0; t < nb; ++t) {
+        const int b = order[t], cls = b / 2, kind = b % 2;
+        const int width = kind == 0 ? class_width(cls) : class_width(cls) / 2;
+        // the ops-batch plans; a bulk batch's widest CRT bucket, which ends it, its own
+        const int pkind = (kind == 1 && t == 0 && nops >= kBulkOps) ? 4 : kind + 2;
+        if (!resolve(width, pkind, &plan[t])) return RSA_ELIMBS;
+        // the bucket that ends a bulk batch: two pairs of waves per
+        // workgroup where its halves have 8 or 16 lanes (see crt_pairs)
+        pairs[t] = pkind == 4 ? crt_pairs(plan[t].inst->G) : 1;
+        if (kind == 1 && round_runs) units.u[b] = (unsigned)(64 / plan[t].inst->G);
+    }
     const unsigned op_blocks = (unsigned)((nops + 255) / 256);
     const OpDesc *od = reinterpret_cast<const OpDesc *>(ops);
     hipLaunchKernelGGL(k_bucket_clear, dim3((unsigned)((kWsHeader / sizeof(unsigned) + 255) / 256)), dim3(256), 0,
                        stream, hdr);
     hipLaunchKernelGGL(k_bucket_count, dim3(op_blocks), dim3(256), 0, stream, od, (unsigned long long)nops, ks->keys,
                        nkeys, (unsigned long long)in_words, (unsigned long long)out_words, slots, errs);
-    hipLaunchKernelGGL(k_bucket_scan, dim3(kMaxBuckets), dim3(kKeySlots), 0, stream, counts, slots);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(kMaxBuckets), dim3(kKeySlots), 0, stream, counts, slots, lists,
+                       (unsigned long long)cap, units);
     hipLaunchKernelGGL(k_bucket_place, dim3(op_blocks), dim3(256), 0, stream, od, (unsigned long long)nops,
                        ks->keys, nkeys, (unsigned long long)in_words, (unsigned long long)out_words, slots, lists,
                        (unsigned long long)cap);
@@ -401,37 +474,17 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         nfork = fs ? (nfork < fs->made ? nfork : fs->made) : 0;    // no fork set: every bucket on `stream`
     }
     if (nfork > 0 && (e = hipEventRecord(fs->fork, stream)) != hipSuccess) return status_of(e);
-    // Bucket order and streams: the CRT buckets of the widest classes are the
-    // longest (their operations are long dependency chains that a bucket's
-    // waves cannot shorten), so each of them gets a keyset stream of its own;
-    // the remaining buckets (narrower CRT classes, then all encryptions,
-    // widest first) follow each other on the caller's stream, beside them,
-    // which then waits for the keyset streams.  The widest CRT bucket's
-    // waves also raise their issue priority: every call ends with its
-    // operations, whose chains are the longest, so on a SIMD shared with other
-    // buckets' waves they issue first.
-    int order[kMaxBuckets], nb = 0;
-    for (int kind = 1; kind >= 0; --kind)
-        for (int cls = num_classes() - 1; cls >= 0; --cls)
-            if (mask & (1u << cls)) order[nb++] = cls * 2 + kind;
     int forked = 0;
     for (int t = 0; t < nb; ++t) {
-        const int b = order[t], cls = b / 2, kind = b % 2;
-        const int width = kind == 0 ? class_width(cls) : class_width(cls) / 2;
-        // the ops-batch plans; a bulk batch's widest CRT bucket, which ends it, its own
-        const int pkind = (kind == 1 && t == 0 && nops >= kBulkOps) ? 4 : kind + 2;
-        Resolved r;
-        if (!resolve(width, pkind, &r)) return RSA_ELIMBS;
-        // the bucket that ends a bulk batch: two pairs of waves per
-        // workgroup where its halves have 8 or 16 lanes (see crt_pairs)
-        const int pairs = pkind == 4 ? crt_pairs(r.inst->G) : 1;
-        int per = r.inst->blocks_per_cu(kind, r.w, pairs);
+        const int b = order[t], kind = b % 2;
+        const Resolved &r = plan[t];
+        int per = r.inst->blocks_per_cu(kind, r.w, pairs[t]);
         if (per <= 0) per = 1;
         const int blocks = per * cus;
         const bool fork = kind == 1 && t < nfork;
         hipStream_t s = fork ? fs->streams[t] : stream;
         if (fork && (e = hipStreamWaitEvent(s, fs->fork, 0)) != hipSuccess) return status_of(e);
-        const ops_launcher fn = kind == 0 ? r.inst->ops_enc : (pairs > 1 ? r.inst->ops_crt_pairs : r.inst->ops_crt);
+        const ops_launcher fn = kind == 0 ? r.inst->ops_enc : (pairs[t] > 1 ? r.inst->ops_crt_pairs : r.inst->ops_crt);
         e = fn(ks->keys, reinterpret_cast<const OpDesc *>(ops), lists + (size_t)b * cap, counts + b, counters + b,
                in_pool, out_pool, r.w, blocks, (kind == 1 && t == 0) ? 1 : 0, s);
         if (e != hipSuccess) return status_of(e);

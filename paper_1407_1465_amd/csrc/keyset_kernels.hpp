@@ -130,8 +130,9 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
         const unsigned base = claim(counter, NG);
         if (base >= count) break;                     // wave-uniform exit
         const unsigned idx = base + g;
-        const bool live = idx < count;
-        const OpDesc op = ops[live ? list[idx] : list[base]];
+        const unsigned at = idx < count ? list[idx] : kOrderHole;
+        const bool live = at != kOrderHole;
+        const OpDesc op = ops[live ? at : list[base]];   // a wave's first entry is never a hole
         const KeyDev &k = keys[op.key_id];
         const ModConsts &mc = k.cn[radix_slot<B>()];
         uint32_t n[L], x[L], one[L], r2[L], xt[L], A[L];
@@ -157,9 +158,10 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
 // crt_pairs) claims P * NG operations at a time (NG = 64 / G), each pair a
 // run of NG of them: the pair's wave 0 takes their halves modulo p, its wave
 // 1 those modulo q, one operation per lane group, so a run of one key's
-// operations (the bucket lists are ordered by key) gives each wave a single
-// exponent.  m_q reaches the pair's wave 0 through its wave 1's LDS region;
-// wave 0 recombines and stores.
+// operations (the bucket lists are ordered by key, each key's run starting a
+// run of NG where that fits) gives each wave a single exponent; entries
+// kOrderHole (the rest of such a run) are skipped.  m_q reaches the pair's
+// wave 0 through its wave 1's LDS region; wave 0 recombines and stores.
 template <int H, int G, int B, int P>
 __global__ __launch_bounds__(128 * P) void k_ops_crt(const KeyDev *__restrict__ keys, const OpDesc *__restrict__ ops,
                                                      const unsigned *__restrict__ list, const unsigned *count_p,
@@ -187,8 +189,9 @@ __global__ __launch_bounds__(128 * P) void k_ops_crt(const KeyDev *__restrict__ 
         const unsigned base = chunk;
         if (base >= count) break;                     // the same for every wave
         const unsigned idx = base + pair * NG + g;
-        const bool live = idx < count;
-        const OpDesc op = ops[live ? list[idx] : list[base]];
+        const unsigned at = idx < count ? list[idx] : kOrderHole;
+        const bool live = at != kOrderHole;
+        const OpDesc op = ops[live ? at : list[base]];   // a wave's first entry is never a hole
         const KeyDev &k = keys[op.key_id];
         const int hl = k.hwords, full = 2 * hl;
         const ModConsts &mc = half ? k.cq[radix_slot<B>()] : k.cp[radix_slot<B>()];
