@@ -2,9 +2,9 @@
 through the C ABI: bit-exact equal to rsa_decrypt_crt_batch on two calls in a
 row, the second with a smaller batch (the static scratch keeps the first
 call's contents), on 2048-, 1024- and 4096-bit keys (the last with two p/q
-wave pairs per workgroup) with ragged batch sizes, and
-captured into a HIP graph on a stream that never ran the call, replayed with
-eager work between replays."""
+wave pairs per workgroup) with ragged batch sizes, at the largest batch it
+takes, and captured into a HIP graph on a stream that never ran the call,
+replayed with eager work between replays."""
 import numpy as np
 import pytest
 
@@ -53,6 +53,33 @@ def test_static_entry_point_equals_allocating_one(bits, nkeys, first, second, se
     rsagpu.decrypt_crt_static(c2, *ops2, out=got2)
     torch.cuda.synchronize()
     assert torch.equal(got2, want2)
+    assert rsagpu.device_errors() == 0
+
+
+def test_static_entry_point_at_its_largest_batch():
+    """RSA_CRT_STATIC_MAX_COUNT messages under 7 keys (64-bit moduli): the key
+    order fills the whole static scratch (its padded runs would not fit, so
+    it stays dense) and the result equals the allocating call's; a sample
+    against the oracle."""
+    rsagpu.init()
+    count, nkeys = rsagpu.CRT_STATIC_MAX_COUNT, 7
+    keys = W.make_keys(64, 6464, nkeys)
+    L = keys[0].limbs
+    key_of = (np.arange(count) * 5 + 1) % nkeys
+    C = np.zeros((count, L), dtype=np.uint32)
+    for j, k in enumerate(keys):
+        idx = np.nonzero(key_of == j)[0]
+        C[idx] = W.uniform_below(k.n, idx.size, W.derive_seed(6464, j, 9), L)
+    ops = [dev(a) for a in crt_operands(keys, key_of, L)]
+    c = dev(C)
+    want = rsagpu.decrypt_crt(c, *ops)
+    got = torch.zeros_like(c)
+    rsagpu.decrypt_crt_static(c, *ops, out=got)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    idx = np.arange(0, count, 16411)
+    exp = oracle_modexp(C[idx], full_operands(keys, key_of[idx], L, "d"), full_operands(keys, key_of[idx], L, "n"))
+    assert np.array_equal(host(got)[idx], exp)
     assert rsagpu.device_errors() == 0
 
 
