@@ -86,6 +86,40 @@ def test_keyset_mixed_vs_oracle():
     ks.close()
 
 
+@pytest.mark.parametrize("crt_runs,encs", [
+    ([3] * 12, 4),          # 12 keys' runs rounded up to whole waves exceed the list: runs back to back
+    ([5, 33, 1], 160),      # the rounded runs fit: each key's run starts a wave, the gaps hold empty slots
+])
+def test_ops_batch_crt_key_runs(crt_runs, encs):
+    """A CRT bucket whose per-key runs are not whole waves, shuffled among
+    encryptions of the same keys: every output equals the oracle's, whether
+    the bucket list holds the runs padded to whole waves or back to back."""
+    keys = W.make_keys(512, 5120 + len(crt_runs), len(crt_runs))
+    rng = random.Random(len(crt_runs))
+    descs = [(1, k) for k, n in enumerate(crt_runs) for _ in range(n)]
+    descs += [(0, rng.randrange(len(keys))) for _ in range(encs)]
+    rng.shuffle(descs)
+    kinds, kids, offs, pool = [], [], [], []
+    off = 0
+    for kd, kid in descs:
+        k = keys[kid]
+        kinds.append(kd)
+        kids.append(kid)
+        offs.append(off)
+        pool.extend(W.int_to_limbs(rng.randrange(k.n), k.limbs).tolist())
+        off += k.limbs
+    kinds, kids, offs = np.array(kinds), np.array(kids), np.array(offs)
+    pool = np.array(pool, dtype=np.uint32)
+    ks = make_keyset(keys)
+    out = run_ops(ks, kinds, kids, offs, pool, off)
+    want = oracle_ops(keys, kinds, kids, offs, pool)
+    L = keys[0].limbs
+    for i in range(len(kinds)):
+        assert np.array_equal(out[offs[i]:offs[i] + L], want[i]), "op %d (kind %d)" % (i, kinds[i])
+    assert rsagpu.device_errors() == 0
+    ks.close()
+
+
 def test_keyset_sixteen_lane_plans_vs_oracle():
     """Ops-batch plans on the 16-lane instances whose limb count is not the
     keyset's (S = 80 for 2048-bit operands, 64 for 1536-bit): the kernels
