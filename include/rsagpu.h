@@ -137,12 +137,12 @@ int rsa_decrypt_crt_batch_static(const uint32_t *c, const uint32_t *p, const uin
  * (padded_limbs / G), window width in exponent bits (a sliding window over
  * the 2^(window_bits-1) odd powers, paper Section 3.6.5) and the LDS bytes
  * per wave.  The CRT kernels run a wave per half, in workgroups of one
- * pair of waves, or of two pairs (one wave per SIMD of a CU) where
- * lanes_per_op is 8 or 16 in rsa_decrypt_crt_batch (kind 1) and in the
- * bucket that ends a bulk rsa_ops_batch call (kind 4), and in
- * rsa_decrypt_crt_batch calls of fewer lanes that need one to two one-pair
- * workgroups per CU where the LDS holds two pairs: a workgroup takes 2 or 4
- * times lds_bytes.
+ * pair of waves, or of two pairs (one wave per SIMD of a CU): in
+ * rsa_decrypt_crt_batch (kind 1) where lanes_per_op is 8 or 16, and for
+ * fewer lanes in calls that need one to two one-pair workgroups per CU; in
+ * every CRT bucket of a bulk rsa_ops_batch call (at least 16384
+ * operations); each only where the LDS holds two pairs.  A workgroup takes
+ * 2 or 4 times lds_bytes.
  * kind: 0 = plain exponentiation (rsa_modexp_batch), 1 = CRT half
  * (rsa_decrypt_crt_batch, modulus of `limbs` limbs), 2 and 3 = the same
  * operations inside rsa_ops_batch (separate plans: its buckets are smaller

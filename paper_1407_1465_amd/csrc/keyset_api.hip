@@ -416,9 +416,10 @@ extern "C" int rsa_ops_batch(rsa_keyset *ks, const rsa_op *ops, size_t nops, con
         // the ops-batch plans; a bulk batch's widest CRT bucket, which ends it, its own
         const int pkind = (kind == 1 && t == 0 && nops >= kBulkOps) ? 4 : kind + 2;
         if (!resolve(width, pkind, &plan[t])) return RSA_ELIMBS;
-        // the bucket that ends a bulk batch: two pairs of waves per
-        // workgroup where its halves have 8 or 16 lanes (see crt_pairs)
-        pairs[t] = pkind == 4 ? crt_pairs(plan[t].inst->G) : 1;
+        // the CRT buckets of a bulk batch: two pairs of waves per workgroup
+        // where the LDS holds them (see crt_pairs)
+        const Instance *in = plan[t].inst;
+        pairs[t] = kind == 1 && nops >= kBulkOps && crt_lds_fits(in->S, in->G, in->B, plan[t].w, 2) ? 2 : 1;
         if (kind == 1 && round_runs) units.u[b] = (unsigned)(64 / plan[t].inst->G);
     }
     const unsigned op_blocks = (unsigned)((nops + 255) / 256);

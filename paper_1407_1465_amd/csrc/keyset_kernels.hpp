@@ -153,9 +153,9 @@ __global__ __launch_bounds__(64) RSAGPU_EXP_OCC(S / G) void k_ops_enc(const KeyD
 }
 
 // Bucket of CRT decryptions for keys of one width class: H limbs of radix
-// 2^B hold p and q.  A workgroup of P pairs of waves (P = 1, or 2 for the
-// bucket that ends a bulk batch where a half has 8 or 16 lanes, see
-// crt_pairs) claims P * NG operations at a time (NG = 64 / G), each pair a
+// 2^B hold p and q.  A workgroup of P pairs of waves (P = 1, or 2 in the
+// CRT buckets of a bulk batch where the LDS holds them, see crt_pairs)
+// claims P * NG operations at a time (NG = 64 / G), each pair a
 // run of NG of them: the pair's wave 0 takes their halves modulo p, its wave
 // 1 those modulo q, one operation per lane group, so a run of one key's
 // operations (the bucket lists are ordered by key, each key's run starting a

@@ -89,11 +89,13 @@ inline size_t lds_bytes_for(int S, int G, int B, int w)
 // per SIMD, and half as many workgroups cover a batch.  This is the least
 // the plain CRT kernel (k_crt) takes (rsa_decrypt_crt_batch picks 2 for
 // fewer lanes too where a batch needs one to two workgroups of one pair per
-// CU) and, in rsa_ops_batch, what the bucket that ends a bulk batch takes
-// (plan kind 4); its other CRT buckets keep one pair: beside
-// other buckets' waves a four-wave workgroup waits longer for a CU with room
-// on every SIMD (served requests' p99 latency rose from 25 to 31-33 ms with
-// two pairs in every bucket).
+// CU).  In rsa_ops_batch every CRT bucket of a bulk call (at least kBulkOps
+// operations) takes two pairs where the LDS holds them, whatever its lanes
+// (the mixed 32768-operation batch 12.4 -> 10.5 ms with tuned plans); the
+// buckets of smaller calls keep one pair: beside other buckets' waves a
+// four-wave workgroup waits longer for a CU with room on every SIMD (served
+// requests' p99 latency rose from 25 to 31-33 ms with two pairs in every
+// bucket of every call).
 __host__ __device__ constexpr int crt_pairs(int G) { return G >= 8 ? 2 : 1; }
 
 // A slot of a CRT processing order that holds no message (the padding that
@@ -136,8 +138,8 @@ hipError_t launch_ops_crt(const KeyDev *keys, const OpDesc *ops, const unsigned 
                           unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                           int urgent, hipStream_t stream);
 
-// The ops-batch CRT kernel with crt_pairs(G) pairs per workgroup (the same
-// kernel as launch_ops_crt where that is 1).
+// The ops-batch CRT kernel with two pairs per workgroup (invalid where the
+// LDS does not hold them).
 template <int S, int G, int B>
 hipError_t launch_ops_crt_pairs(const KeyDev *keys, const OpDesc *ops, const unsigned *list, const unsigned *count,
                                 unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,

@@ -68,15 +68,10 @@ hipError_t launch_ops_crt_pairs(const KeyDev *keys, const OpDesc *ops, const uns
                                 unsigned *counter, const uint32_t *in_pool, uint32_t *out_pool, int w, int blocks,
                                 int urgent, hipStream_t stream)
 {
-    if constexpr (crt_pairs(G) == 1) {
-        return launch_ops_crt<S, G, B>(keys, ops, list, count, counter, in_pool, out_pool, w, blocks, urgent, stream);
-    } else {
-        constexpr int P = crt_pairs(G);
-        if (!crt_lds_fits(S, G, B, w, P)) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_ops_crt<S, G, B, P>), dim3(blocks), dim3(128 * P), 2 * P * lds_bytes_for(S, G, B, w),
-                           stream, keys, ops, list, count, counter, in_pool, out_pool, w, urgent);
-        return hipGetLastError();
-    }
+    if (!crt_lds_fits(S, G, B, w, 2)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_ops_crt<S, G, B, 2>), dim3(blocks), dim3(256), 4 * lds_bytes_for(S, G, B, w), stream, keys,
+                       ops, list, count, counter, in_pool, out_pool, w, urgent);
+    return hipGetLastError();
 }
 
 template <int S, int G, int B>
@@ -94,13 +89,10 @@ int ops_blocks_per_cu(int kind, int w, int pairs)
                                                              2 * lds);
             return e == hipSuccess ? nb : 0;
         }
-        if constexpr (crt_pairs(G) > 1) {
-            if (pairs > 1)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B, crt_pairs(G)>), 128 * crt_pairs(G),
-                    2 * crt_pairs(G) * lds);
-        }
-        if (e != hipSuccess)
+        if (pairs > 1)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B, 2>),
+                                                             256, 4 * lds);
+        else
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k_ops_crt<S, G, B, 1>),
                                                              128, 2 * lds);
     }

@@ -15,7 +15,7 @@ struct Instance {
     setup_launcher setup;
     ops_launcher ops_enc;
     ops_launcher ops_crt;
-    ops_launcher ops_crt_pairs;       // crt_pairs(G) pairs per workgroup (the bucket ending a bulk batch)
+    ops_launcher ops_crt_pairs;       // two pairs per workgroup (the CRT buckets of a bulk batch)
     ops_occupancy blocks_per_cu;
 };
 
