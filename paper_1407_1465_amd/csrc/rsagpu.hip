@@ -75,10 +75,16 @@ struct Plan {
 // for the other buckets' waves) pay off.  Kind 4 is the CRT half of the
 // widest class of a bulk ops batch (rsa_ops_batch with at least
 // kBulkOps operations), whose end waits for that bucket's last operations.
-// For 4096-bit keys both take 16 lanes (S = 80): one operation's chain is
+// For 4096-bit keys kind 3 takes 16 lanes (S = 80): one operation's chain is
 // ~1.6x shorter than on 8 lanes for ~1.2x the lane-instructions, and a
-// serving batch, like a bulk one, ends with its 4096-bit decryptions (p99
-// 50 -> 34 ms against 8 lanes at the same request rate).  The plain CRT call
+// serving batch ends with its 4096-bit decryptions (p99 50 -> 34 ms against
+// 8 lanes at the same request rate).  Kind 4 takes 8 lanes: in a bulk
+// batch every CRT bucket runs two wave pairs per workgroup, and 4096-bit
+// halves on 8 lanes are half as many waves (274 for the mixed batch's 1092
+// operations, in 69 four-wave workgroups), which leaves SIMDs to the other
+// buckets (the mixed batch 12.12 -> 10.46-10.62 ms with its other plans at
+// their defaults, served requests 7536 -> 8326/s through faster bulk
+// bursts; a 5-bit window 10.98 ms).  The plain CRT call
 // takes 16 lanes and a 5-bit window for 4096-bit keys too: with two wave
 // pairs per workgroup, 256, 1092 and 4368 decryptions took 6.2, 7.1 and
 // 17.3 ms against 9.8, 10.9 and 20.4 ms on 8 lanes with a 4-bit window.
@@ -99,7 +105,7 @@ static const Plan kDefault[kKinds][kNumClasses] = {
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
      {29, 16, 4}, {29, 16, 4}, {29, 16, 3}},
     {{32, 1, 5}, {32, 1, 5}, {32, 1, 4}, {32, 2, 4}, {32, 4, 5}, {29, 4, 4}, {29, 2, 4}, {29, 8, 5},
-     {29, 16, 4}, {29, 16, 4}, {29, 16, 3}},
+     {29, 8, 4}, {29, 16, 4}, {29, 16, 3}},
 };
 
 static int pack(const Plan &p) { return p.B << 16 | p.G << 8 | p.w; }

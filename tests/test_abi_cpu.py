@@ -110,17 +110,19 @@ def test_ops_batch_plans_are_separate():
         rsagpu.set_plan(32, 3, 0, 0, 0)
         rsagpu.set_plan(64, 2, 0, 0, 0)
     # kind 4: the widest CRT bucket of a bulk ops batch; 4096-bit halves on
-    # 16 lanes (S = 80) there, in other ops batches and in the plain CRT call
-    # (there with a 5-bit window)
+    # 8 lanes there (every CRT bucket of a bulk batch runs two wave pairs per
+    # workgroup), on 16 lanes (S = 80) in other ops batches and in the plain
+    # CRT call (there with a 5-bit window)
     p4, p3, p1 = rsagpu.get_plan(64, 4), rsagpu.get_plan(64, 3), rsagpu.get_plan(64, 1)
-    assert (p4.radix_bits, p4.padded_limbs, p4.lanes_per_op) == (29, 80, 16)
+    assert (p4.radix_bits, p4.padded_limbs, p4.lanes_per_op, p4.window_bits) == (29, 72, 8, 4)
     assert (p3.radix_bits, p3.padded_limbs, p3.lanes_per_op) == (29, 80, 16)
     assert (p1.lanes_per_op, p1.window_bits) == (16, 5)
-    rsagpu.set_plan(64, 4, 29, 8, 4)
+    rsagpu.set_plan(64, 4, 29, 16, 4)
     try:
         assert rsagpu.get_plan(64, 3) == p3                    # kinds 3 and 4 are set apart
     finally:
         rsagpu.set_plan(64, 4, 0, 0, 0)
+    assert rsagpu.get_plan(64, 4) == p4
     for kind in (-1, 5):
         with pytest.raises(Exception):
             rsagpu.get_plan(32, kind)
