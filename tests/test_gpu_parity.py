@@ -237,6 +237,27 @@ def test_crt_key_runs_of_any_length(bits, runs):
     assert rsagpu.device_errors() == 0
 
 
+def test_crt_two_pair_workgroups_for_two_lane_halves():
+    """8736 1024-bit messages under 16 keys (546 per key, not whole waves):
+    273 wave pairs of 2-lane halves, between one and two one-pair workgroups
+    per CU, so the call runs two pairs per workgroup where the kernel's
+    occupancy allows it, over a key order padded to whole waves.  Every
+    element equals the oracle's plain C^d mod n."""
+    count, nk = 8736, 16
+    keys = W.make_keys(1024, W.SEED_BASE + 4, nk)
+    L = keys[0].limbs
+    key_of = np.arange(count) % nk
+    C = np.zeros((count, L), dtype=np.uint32)
+    for j, k in enumerate(keys):
+        idx = np.nonzero(key_of == j)[0]
+        C[idx] = W.uniform_below(k.n, idx.size, W.derive_seed(8736, j, 1), L)
+    out = host(rsagpu.decrypt_crt(dev(C), *[dev(a) for a in crt_operands(keys, key_of, L)]))
+    want = oracle_modexp(C, full_operands(keys, key_of, L, "d"), full_operands(keys, key_of, L, "n"))
+    bad = np.nonzero((out != want).any(axis=1))[0]
+    assert bad.size == 0, "%d mismatches, first at %d" % (bad.size, bad[0] if bad.size else -1)
+    assert rsagpu.device_errors() == 0
+
+
 @pytest.mark.parametrize("table", [1, 2])
 def test_paper_table_keys_round_trip(table):
     """The paper's Section 10 experiment on one-word keys: every encryption
