@@ -237,6 +237,55 @@ def test_crt_key_runs_of_any_length(bits, runs):
     assert rsagpu.device_errors() == 0
 
 
+def _order_bucket(key, hl):
+    """The plain CRT call's 16-bit grouping hash of a key (its words p[0],
+    p[1], dp[0], dq[0]), restated here only to pick keys whose buckets meet."""
+    m = 0xFFFFFFFF
+    rotl = lambda x, r: ((x << r) | (x >> (32 - r))) & m
+    p, dp, dq = (W.int_to_limbs(v, hl) for v in (key.p, key.dp, key.dq))
+    h = (int(p[0]) * 0x9E3779B1) & m
+    h ^= (((int(p[1]) if hl > 1 else 0) + 0x7F4A7C15) & m) * 0x85EBCA77 & m
+    h = rotl(h, 13) ^ ((int(dp[0]) * 0xC2B2AE3D) & m)
+    h = rotl(h, 11) ^ ((int(dq[0]) * 0x27D4EB2F) & m)
+    h ^= h >> 15
+    h = (h * 0x2C1B3C6D) & m
+    h ^= h >> 12
+    return h >> 16
+
+
+def test_crt_keys_whose_buckets_meet():
+    """Two keys whose grouping hashes meet (found among 400 seeded 256-bit
+    keys), with 37 and 50 messages (not whole waves), shuffled with three
+    other keys: the two share one run, so its waves hold both keys' halves
+    and take the per-group schedule, and every element still equals the
+    oracle's plain C^d mod n, through both CRT entry points."""
+    pool = W.make_keys(256, 7777, 400)
+    hl = pool[0].limbs // 2
+    seen, pair = {}, None
+    for i, k in enumerate(pool):
+        b = _order_bucket(k, hl)
+        if b in seen:
+            pair = (seen[b], i)
+            break
+        seen[b] = i
+    assert pair is not None, "no two seeded keys share a bucket"
+    keys = [pool[pair[0]], pool[pair[1]], pool[0], pool[1], pool[2]]
+    runs = [37, 50, 5, 64, 70]
+    L = keys[0].limbs
+    key_of = np.repeat(np.arange(len(keys)), runs)
+    np.random.default_rng(7).shuffle(key_of)
+    r = random.Random(8)
+    C = W.ints_to_limbs([r.randrange(keys[k].n) for k in key_of], L)
+    ops = [dev(a) for a in crt_operands(keys, key_of, L)]
+    out = host(rsagpu.decrypt_crt(dev(C), *ops))
+    want = oracle_modexp(C, full_operands(keys, key_of, L, "d"), full_operands(keys, key_of, L, "n"))
+    wrong = np.nonzero((out != want).any(axis=1))[0]
+    assert wrong.size == 0, "%d mismatches, first at %d" % (wrong.size, wrong[0])
+    static = host(rsagpu.decrypt_crt_static(dev(C), *ops, out=torch.empty_like(dev(C))))
+    assert np.array_equal(static, out)
+    assert rsagpu.device_errors() == 0
+
+
 def test_crt_two_pair_workgroups_for_two_lane_halves():
     """8736 1024-bit messages under 16 keys (546 per key, not whole waves):
     273 wave pairs of 2-lane halves, between one and two one-pair workgroups
