@@ -120,6 +120,49 @@ def test_ops_batch_crt_key_runs(crt_runs, encs):
     ks.close()
 
 
+@pytest.mark.parametrize("window", [0, 6])
+def test_bulk_batch_crt_bucket_pairs_and_fallback(window):
+    """In a bulk batch (at least 16384 operations) every CRT bucket runs two
+    wave pairs per workgroup where the LDS holds them: 16128 512-bit CRT
+    decryptions beside 256 operations of a wider key (so the 512-bit bucket
+    takes the kind-3 plan), on the default plan (two pairs fit) and on a
+    6-bit window whose tables fit one pair only (the bucket falls back to
+    one); every output against the oracle."""
+    small = W.make_keys(512, 5150, 3)
+    keys = small + W.make_keys(1024, W.SEED_BASE + 4, 16)[:1]
+    lds_limit = 160 * 1024
+    if window:
+        rsagpu.set_plan(8, 3, 32, 1, window)
+    try:
+        lds = rsagpu.get_plan(8, 3).lds_bytes
+        assert (4 * lds + 16 <= lds_limit) == (window == 0)
+        rng = random.Random(window + 11)
+        descs = [(1, i % 3) for i in range(16128)] + [(i % 2, 3) for i in range(256)]
+        rng.shuffle(descs)
+        kinds, kids, offs, pool = [], [], [], []
+        off = 0
+        for kd, kid in descs:
+            k = keys[kid]
+            kinds.append(kd)
+            kids.append(kid)
+            offs.append(off)
+            pool.extend(W.int_to_limbs(rng.randrange(k.n), k.limbs).tolist())
+            off += k.limbs
+        kinds, kids, offs = np.array(kinds), np.array(kids), np.array(offs)
+        pool = np.array(pool, dtype=np.uint32)
+        ks = make_keyset(keys)
+        out = run_ops(ks, kinds, kids, offs, pool, off)
+        want = oracle_ops(keys, kinds, kids, offs, pool)
+        bad = [i for i in range(len(kinds))
+               if not np.array_equal(out[offs[i]:offs[i] + keys[kids[i]].limbs], want[i])]
+        assert not bad, "%d of %d differ, first %d" % (len(bad), len(kinds), bad[0])
+        assert rsagpu.device_errors() == 0
+        ks.close()
+    finally:
+        if window:
+            rsagpu.set_plan(8, 3, 0, 0, 0)
+
+
 def test_keyset_sixteen_lane_plans_vs_oracle():
     """Ops-batch plans on the 16-lane instances whose limb count is not the
     keyset's (S = 80 for 2048-bit operands, 64 for 1536-bit): the kernels
